@@ -1,0 +1,225 @@
+"""CPU oracle for full-pivot Gauss-Jordan inversion -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never calls it,
+and it shares no code with the HIP path: the only thing the two have in
+common is the seeded inputs they are handed.
+
+The arithmetic lives in ``gj_oracle.c`` (plain C, one element at a time,
+correctly rounded division and one ``fma`` per eq. 15 element, following the
+paper's section 2: eqs. 1-2 initialisation, Obs. 2-3 pivot search and swaps,
+eq. 14 pivot-row scaling, eq. 15 elimination, eq. 13 determinant, Obs. 3
+depivoting).  This module loads it through ctypes and adds the few pieces
+that are plain definitions written out in NumPy / Python:
+
+* ``newton_schulz`` -- the refinement X <- X + X (I - A X), matmul as the
+  only library step (parity: pinned by the contraction property
+  R_{k+1} = R_k^2 checked in the tests);
+* ``residual`` -- ||A X - I||_F / (||A||_F ||X||_F);
+* ``cofactor_det`` -- exact rational Laplace expansion (n <= 7), the
+  brute-force determinant pin;
+* ``perms_from_pivots`` -- original-index permutations from ipiv / jpiv.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gj_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+RES_OK, RES_SINGULAR, RES_NONFINITE, RES_REFINE_FALLBACK = 0, 1, 2, 3
+
+
+class OraResult(ctypes.Structure):
+    _fields_ = [
+        ("code", ctypes.c_int32),
+        ("rank", ctypes.c_int32),
+        ("det_sign", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32),
+        ("det_mant", ctypes.c_double),
+        ("det_exp", ctypes.c_int64),
+        ("det", ctypes.c_double),
+        ("logabsdet", ctypes.c_double),
+        ("resid", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        for name in ("ora_gj_invert_f64", "ora_gj_invert_f32", "ora_gj_invert_f80",
+                     "ora_gj_augmented_f64"):
+            fn = getattr(lib, name)
+            fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P, P, P,
+                           ctypes.POINTER(OraResult)]
+            fn.restype = ctypes.c_int
+        lib.ora_lu_static_det_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P,
+                                              ctypes.POINTER(OraResult)]
+        lib.ora_lu_static_det_f64.restype = ctypes.c_int
+        lib.ora_result_size.restype = ctypes.c_int
+        assert lib.ora_result_size() == ctypes.sizeof(OraResult)
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _run(fname: str, A: np.ndarray, zero_tol: float, in_dtype, out_dtype):
+    A = np.ascontiguousarray(A, dtype=in_dtype)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A must be square")
+    n = A.shape[0]
+    X = np.empty((n, n), dtype=out_dtype)
+    ipiv = np.full(n, -1, dtype=np.int32)
+    jpiv = np.full(n, -1, dtype=np.int32)
+    res = OraResult()
+    getattr(_load(), fname)(n, _ptr(A), n, float(zero_tol), _ptr(X), _ptr(ipiv), _ptr(jpiv),
+                            ctypes.byref(res))
+    return X, ipiv, jpiv, res.as_dict()
+
+
+def gj_invert_f64(A, zero_tol: float = -1.0):
+    """FP64 in-place full-pivot GJ.  Returns (X, ipiv, jpiv, result dict)."""
+    return _run("ora_gj_invert_f64", A, zero_tol, np.float64, np.float64)
+
+
+def gj_invert_f32(A, zero_tol: float = 0.0):
+    """FP32 model of the same algorithm (default zero threshold: exact 0)."""
+    return _run("ora_gj_invert_f32", A, zero_tol, np.float32, np.float32)
+
+
+def gj_invert_f80(A, zero_tol: float = -1.0):
+    """Same algorithm in x87 long double (u = 2^-64); X rounded to double."""
+    return _run("ora_gj_invert_f80", A, zero_tol, np.float64, np.float64)
+
+
+def gj_augmented_f64(A, zero_tol: float = -1.0):
+    """Literal eqs. 1-2, 14-15 on separate A and D arrays."""
+    return _run("ora_gj_augmented_f64", A, zero_tol, np.float64, np.float64)
+
+
+def lu_static_det_f64(A, ipiv, jpiv) -> dict:
+    """FP64 determinant by LU with a fixed (previously chosen) pivot order."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
+    jpiv = np.ascontiguousarray(jpiv, dtype=np.int32)
+    res = OraResult()
+    _load().ora_lu_static_det_f64(n, _ptr(A), n, _ptr(ipiv), _ptr(jpiv), ctypes.byref(res))
+    return res.as_dict()
+
+
+def gj_det_f64(A, zero_tol: float = -1.0) -> dict:
+    """Determinant (and pivots) of the FP64 full-pivot run."""
+    _, ipiv, jpiv, res = gj_invert_f64(A, zero_tol)
+    res = dict(res)
+    res["ipiv"], res["jpiv"] = ipiv, jpiv
+    return res
+
+
+def residual(A, X) -> float:
+    """Normwise residual ||A X - I||_F / (||A||_F ||X||_F) in FP64."""
+    A = np.asarray(A, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    R = A @ X - np.eye(A.shape[0])
+    return float(np.linalg.norm(R) / (np.linalg.norm(A) * np.linalg.norm(X)))
+
+
+def newton_schulz(A, X0, max_iters: int = 10, stall: float = 0.5, accept: float = 1e-6):
+    """Newton-Schulz refinement X <- X + X (I - A X) in FP64.
+
+    The loop: R = I - A X; stop when ||R||_F is no longer below ``stall``
+    times the previous one (the FP64 rounding floor is reached), keeping the
+    iterate with the smaller residual; ``max_iters`` updates at most.  The
+    result is accepted when its relative residual ||R||_F / sqrt(n) is below
+    ``accept``; otherwise the caller falls back to the plain FP64 run.
+    Returns (X, updates, [||R_k||_F for every R computed], accepted).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    X = np.asarray(X0, dtype=np.float64).copy()
+    n = A.shape[0]
+    eye = np.eye(n)
+    R = eye - A @ X
+    r = float(np.linalg.norm(R))
+    norms = [r]
+    updates = 0
+    while updates < max_iters and np.isfinite(r) and r > 0.0:
+        Xn = X + X @ R
+        Rn = eye - A @ Xn
+        rn = float(np.linalg.norm(Rn))
+        norms.append(rn)
+        if not np.isfinite(rn) or rn >= r:
+            break                      # no progress: keep the previous iterate
+        X, R, r = Xn, Rn, rn
+        updates += 1
+        if rn > stall * norms[-2]:
+            break                      # the rounding floor is reached
+    accepted = bool(np.isfinite(r) and r / np.sqrt(n) < accept)
+    return X, updates, norms, accepted
+
+
+def cofactor_det(A) -> Fraction:
+    """Exact determinant of the (binary floating point) input by Laplace
+    expansion over rationals.  Brute force; n <= 7."""
+    M = [[Fraction(float(v)) for v in row] for row in np.asarray(A, dtype=np.float64)]
+    n = len(M)
+    if n > 7:
+        raise ValueError("cofactor expansion is for n <= 7")
+
+    def det(rows, cols):
+        if len(rows) == 1:
+            return M[rows[0]][cols[0]]
+        total = Fraction(0)
+        r0 = rows[0]
+        for idx, c in enumerate(cols):
+            if M[r0][c] == 0:
+                continue
+            minor = det(rows[1:], cols[:idx] + cols[idx + 1:])
+            total += (-1) ** idx * M[r0][c] * minor
+        return total
+
+    return det(list(range(n)), list(range(n)))
+
+
+def perms_from_pivots(ipiv, jpiv):
+    """Original-index row and column orders after applying the swaps:
+    the pivoted matrix is A[rows][:, cols]."""
+    n = len(ipiv)
+    rows = np.arange(n)
+    cols = np.arange(n)
+    for k in range(n):
+        r, c = int(ipiv[k]), int(jpiv[k])
+        if r < 0:
+            break
+        rows[[k, r]] = rows[[r, k]]
+        cols[[k, c]] = cols[[c, k]]
+    return rows, cols

@@ -1,0 +1,416 @@
+/*
+ * gj_oracle.c -- plain, slow, obviously correct CPU oracle for full-pivot
+ * Gauss-Jordan inversion (Anghel Drugarin, "Numerical application and Turbo C
+ * program using the Gauss-Jordan method", arXiv:1401.7962).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into liboracle.so, which
+ * only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load.  It shares no code, header or constant with the HIP
+ * library; the two meet only through seeded inputs.
+ *
+ * What is computed (paper section 2):
+ *   - initialisation A^0 = A, D^0 = I                         (eqs. 1-2)
+ *   - at step k: pivot search by maximum |a| over the trailing block, with a
+ *     swap of rows k,i and columns k,j                         (Obs. 2 and 3)
+ *   - the pivot row of A and D divided by the pivot            (eq. 14)
+ *   - every other row i gets -a_ik times the new pivot row     (eq. 15 and the
+ *     prose that follows it: the D update uses the D pivot row)
+ *   - at the end A^n = I, A^-1 = D^n                           (eqs. 11-12)
+ *   - det A = product of the pivots                            (eq. 13)
+ *   - the row and column swaps are undone in reverse order     (Obs. 3 and the
+ *     conclusions)
+ *   - a pivot that is null or below a preset zero threshold, when no other
+ *     candidate is usable, means A is singular                 (Obs. 2)
+ *
+ * Readings of points the paper leaves open (each listed in the design doc):
+ *   - the D half is stored in place in the columns that A no longer needs, so
+ *     one n x n array holds [A|D] (the work-skipping form, eqs. 3-10);
+ *   - eq. 14 uses correctly rounded division; the pivot slot becomes 1/p;
+ *   - eq. 15 is one fused multiply-add per element: w = fma(-q, w_kj, w);
+ *   - ties between equal |a| go to the lowest row, then the lowest column, of
+ *     the current (already swapped) matrix = first maximum in row-major order;
+ *   - the determinant sign is (-1)^(number of non-trivial row and column
+ *     swaps); the product is kept as mantissa in [0.5,1) times 2^e;
+ *   - default zero threshold tau = n * 2^-52 * (largest |a| of A); a step is
+ *     singular if its pivot candidate m satisfies m == 0 or m < tau;
+ *   - any NaN or infinity among the candidates stops the run (NONFINITE).
+ *
+ * The routine is written once as a macro and instantiated for double (the
+ * FP64 oracle), long double (x87 64-bit mantissa: the "truth" used for
+ * forward errors) and float (a CPU model of an FP32 elimination).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* Result record, laid out field by field like the library's public record so
+ * that the same ctypes structure reads both.  Codes: 0 ok, 1 singular,
+ * 2 non-finite, 3 refinement fell back. */
+typedef struct {
+    int32_t code, rank, det_sign, refine_iters;
+    double det_mant;
+    int64_t det_exp;
+    double det, logabsdet, resid;
+} ora_result;
+
+enum { ORA_OK = 0, ORA_SINGULAR = 1, ORA_NONFINITE = 2, ORA_REFINE_FALLBACK = 3 };
+
+static double ora_ldexp64(double m, int64_t e)
+{
+    /* ldexp with a 64-bit exponent: saturate far outside the double range */
+    if (e > 4000) e = 4000;
+    if (e < -4000) e = -4000;
+    return ldexp(m, (int)e);
+}
+
+static void ora_fill_failure(ora_result *res, int code, int rank, int n,
+                             int32_t *ipiv, int32_t *jpiv)
+{
+    res->code = code;
+    res->rank = rank;
+    res->det_sign = 0;
+    res->det_mant = 0.0;
+    res->det_exp = 0;
+    if (code == ORA_SINGULAR) {
+        res->det = 0.0;
+        res->logabsdet = -INFINITY;
+    } else {
+        res->det = NAN;
+        res->logabsdet = NAN;
+    }
+    for (int k = rank; k < n; ++k) {
+        if (ipiv) ipiv[k] = -1;
+        if (jpiv) jpiv[k] = -1;
+    }
+}
+
+/*
+ * GJ_INPLACE(NAME, T, FABS, FMA, FREXP, ISFIN)
+ *
+ * int NAME(int n, const T *A, int64_t lda, double zero_tol,
+ *          T *X, int32_t *ipiv, int32_t *jpiv, ora_result *res)
+ *
+ * A: n x n row-major, leading dimension lda.  X: n x n row-major, ld n,
+ * receives A^-1 (all NaN when the run stops early).  ipiv[k] / jpiv[k]: the
+ * row / column (0-based, of the current matrix) swapped with k at step k,
+ * -1 for steps not taken.  zero_tol < 0 selects the default threshold.
+ * Returns res->code.
+ */
+#define GJ_INPLACE(NAME, T, FABS, FMA, FREXP, ISFIN, EPS_DEFAULT)                  \
+int NAME(int n, const T *A, int64_t lda, double zero_tol, T *X,                    \
+         int32_t *ipiv, int32_t *jpiv, ora_result *res)                            \
+{                                                                                  \
+    T *W = X;                                   /* in-place working array */       \
+    for (int i = 0; i < n; ++i)                                                    \
+        for (int j = 0; j < n; ++j)                                                \
+            W[(int64_t)i * n + j] = A[(int64_t)i * lda + j];   /* eqs. 1-2 */      \
+    int sign = 1;                                                                  \
+    T m_acc = (T)1;                                                                \
+    int64_t e_acc = 0;                                                             \
+    T tau = (T)zero_tol;                                                           \
+    res->refine_iters = 0;                                                         \
+    res->resid = NAN;                                                              \
+    for (int k = 0; k < n; ++k) {                                                  \
+        /* pivot search over the trailing block, first maximum in row-major   */  \
+        /* order (Obs. 2 and 3)                                               */  \
+        T best = (T)-1;                                                            \
+        int r = -1, c = -1, nonfinite = 0;                                         \
+        for (int i = k; i < n; ++i)                                                \
+            for (int j = k; j < n; ++j) {                                          \
+                T v = FABS(W[(int64_t)i * n + j]);                                 \
+                if (!ISFIN(v)) nonfinite = 1;                                      \
+                if (v > best) { best = v; r = i; c = j; }                          \
+            }                                                                      \
+        if (nonfinite) {                                                           \
+            ora_fill_failure(res, ORA_NONFINITE, k, n, ipiv, jpiv);                \
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) W[t] = (T)NAN;            \
+            return ORA_NONFINITE;                                                  \
+        }                                                                          \
+        if (k == 0 && zero_tol < 0)                                                \
+            tau = (T)n * (T)(EPS_DEFAULT) * best;   /* preset zero threshold */    \
+        if (best == (T)0 || best < tau) {           /* Obs. 2: singular */         \
+            ora_fill_failure(res, ORA_SINGULAR, k, n, ipiv, jpiv);                 \
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) W[t] = (T)NAN;            \
+            return ORA_SINGULAR;                                                   \
+        }                                                                          \
+        ipiv[k] = r;                                                               \
+        jpiv[k] = c;                                                               \
+        if (r != k) {                               /* swap rows k and r */        \
+            for (int j = 0; j < n; ++j) {                                          \
+                T t = W[(int64_t)k * n + j];                                       \
+                W[(int64_t)k * n + j] = W[(int64_t)r * n + j];                     \
+                W[(int64_t)r * n + j] = t;                                         \
+            }                                                                      \
+            sign = -sign;                                                          \
+        }                                                                          \
+        if (c != k) {                               /* swap columns k and c */     \
+            for (int i = 0; i < n; ++i) {                                          \
+                T t = W[(int64_t)i * n + k];                                       \
+                W[(int64_t)i * n + k] = W[(int64_t)i * n + c];                     \
+                W[(int64_t)i * n + c] = t;                                         \
+            }                                                                      \
+            sign = -sign;                                                          \
+        }                                                                          \
+        T p = W[(int64_t)k * n + k];                /* the pivot */                \
+        {   /* eq. 13: running product of pivots as mantissa * 2^e */              \
+            int e1, e2;                                                            \
+            T f = FREXP(p, &e1);                                                   \
+            m_acc = m_acc * f;                                                     \
+            e_acc += e1;                                                           \
+            m_acc = FREXP(m_acc, &e2);                                             \
+            e_acc += e2;                                                           \
+        }                                                                          \
+        /* eq. 14: pivot row divided by the pivot; slot (k,k) becomes 1/p */       \
+        W[(int64_t)k * n + k] = (T)1;                                              \
+        for (int j = 0; j < n; ++j)                                                \
+            W[(int64_t)k * n + j] = W[(int64_t)k * n + j] / p;                     \
+        /* eq. 15: every other row minus a_ik times the new pivot row */           \
+        for (int i = 0; i < n; ++i) {                                              \
+            if (i == k) continue;                                                  \
+            T q = W[(int64_t)i * n + k];                                           \
+            W[(int64_t)i * n + k] = (T)0;                                          \
+            for (int j = 0; j < n; ++j)                                            \
+                W[(int64_t)i * n + j] = FMA(-q, W[(int64_t)k * n + j],             \
+                                            W[(int64_t)i * n + j]);                \
+        }                                                                          \
+    }                                                                              \
+    /* undo the swaps in reverse order: row swaps of A come back as column     */  \
+    /* swaps of the result and column swaps of A as row swaps                  */  \
+    for (int k = n - 1; k >= 0; --k) {                                             \
+        int r = ipiv[k], c = jpiv[k];                                              \
+        if (r != k)                                                                \
+            for (int i = 0; i < n; ++i) {                                          \
+                T t = W[(int64_t)i * n + k];                                       \
+                W[(int64_t)i * n + k] = W[(int64_t)i * n + r];                     \
+                W[(int64_t)i * n + r] = t;                                         \
+            }                                                                      \
+        if (c != k)                                                                \
+            for (int j = 0; j < n; ++j) {                                          \
+                T t = W[(int64_t)k * n + j];                                       \
+                W[(int64_t)k * n + j] = W[(int64_t)c * n + j];                     \
+                W[(int64_t)c * n + j] = t;                                         \
+            }                                                                      \
+    }                                                                              \
+    res->code = ORA_OK;                                                            \
+    res->rank = n;                                                                 \
+    res->det_sign = (m_acc < 0) ? -sign : sign;                                    \
+    res->det_mant = (double)FABS(m_acc);                                           \
+    res->det_exp = e_acc;                                                          \
+    res->det = ora_ldexp64((double)sign * (double)m_acc, e_acc);                   \
+    res->logabsdet = log(res->det_mant) + (double)e_acc * 0.69314718055994530942;  \
+    return ORA_OK;                                                                 \
+}
+
+static int isfin_d(double v) { return isfinite(v); }
+static int isfin_l(long double v) { return isfinite(v); }
+static int isfin_f(float v) { return isfinite(v); }
+
+GJ_INPLACE(ora_gj_invert_f64, double, fabs, fma, frexp, isfin_d, 0x1p-52)
+GJ_INPLACE(ora_gj_invert_f32, float, fabsf, fmaf, frexpf, isfin_f, 0.0)
+
+/* long double variant: input and output in double, arithmetic in long
+ * double.  Used as the "truth" for forward errors (unit roundoff 2^-64). */
+GJ_INPLACE(ora_gj_invert_f80_impl, long double, fabsl, fmal, frexpl, isfin_l, 0x1p-52)
+
+int ora_gj_invert_f80(int n, const double *A, int64_t lda, double zero_tol, double *X,
+                      int32_t *ipiv, int32_t *jpiv, ora_result *res)
+{
+    long double *a = (long double *)malloc(sizeof(long double) * (size_t)n * n);
+    long double *x = (long double *)malloc(sizeof(long double) * (size_t)n * n);
+    if (!a || !x) { free(a); free(x); return -1; }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) a[(int64_t)i * n + j] = A[(int64_t)i * lda + j];
+    int code = ora_gj_invert_f80_impl(n, a, n, zero_tol, x, ipiv, jpiv, res);
+    for (int64_t t = 0; t < (int64_t)n * n; ++t) X[t] = (double)x[t];
+    free(a);
+    free(x);
+    return code;
+}
+
+/*
+ * Literal augmented form of eqs. 1-2 and 14-15: A and D held in separate
+ * arrays.  Row swaps act on both halves (a left multiplication), column swaps
+ * on A only.  At the end D = Q^-1 A^-1 where Q is the product of the column
+ * swaps, so A^-1 = Q D: the column swaps come back as row swaps of D, in
+ * reverse order.  Used to check the in-place form against the equations as
+ * printed.
+ */
+int ora_gj_augmented_f64(int n, const double *A, int64_t lda, double zero_tol, double *X,
+                         int32_t *ipiv, int32_t *jpiv, ora_result *res)
+{
+    double *a = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *d = X;
+    if (!a) return -1;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            a[(int64_t)i * n + j] = A[(int64_t)i * lda + j];        /* eq. 1 */
+            d[(int64_t)i * n + j] = (i == j) ? 1.0 : 0.0;          /* eq. 2 */
+        }
+    double tau = zero_tol;
+    int sign = 1;
+    double m_acc = 1.0;
+    int64_t e_acc = 0;
+    res->refine_iters = 0;
+    res->resid = NAN;
+    for (int k = 0; k < n; ++k) {
+        double best = -1.0;
+        int r = -1, c = -1, nonfinite = 0;
+        for (int i = k; i < n; ++i)
+            for (int j = k; j < n; ++j) {
+                double v = fabs(a[(int64_t)i * n + j]);
+                if (!isfinite(v)) nonfinite = 1;
+                if (v > best) { best = v; r = i; c = j; }
+            }
+        if (nonfinite) {
+            ora_fill_failure(res, ORA_NONFINITE, k, n, ipiv, jpiv);
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) d[t] = NAN;
+            free(a);
+            return ORA_NONFINITE;
+        }
+        if (k == 0 && zero_tol < 0) tau = (double)n * 0x1p-52 * best;
+        if (best == 0.0 || best < tau) {
+            ora_fill_failure(res, ORA_SINGULAR, k, n, ipiv, jpiv);
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) d[t] = NAN;
+            free(a);
+            return ORA_SINGULAR;
+        }
+        ipiv[k] = r;
+        jpiv[k] = c;
+        if (r != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = a[(int64_t)k * n + j];
+                a[(int64_t)k * n + j] = a[(int64_t)r * n + j];
+                a[(int64_t)r * n + j] = t;
+                t = d[(int64_t)k * n + j];
+                d[(int64_t)k * n + j] = d[(int64_t)r * n + j];
+                d[(int64_t)r * n + j] = t;
+            }
+            sign = -sign;
+        }
+        if (c != k) {
+            for (int i = 0; i < n; ++i) {
+                double t = a[(int64_t)i * n + k];
+                a[(int64_t)i * n + k] = a[(int64_t)i * n + c];
+                a[(int64_t)i * n + c] = t;
+            }
+            sign = -sign;
+        }
+        double p = a[(int64_t)k * n + k];
+        {
+            int e1, e2;
+            double f = frexp(p, &e1);
+            m_acc = m_acc * f;
+            e_acc += e1;
+            m_acc = frexp(m_acc, &e2);
+            e_acc += e2;
+        }
+        for (int j = 0; j < n; ++j) {                       /* eq. 14 */
+            a[(int64_t)k * n + j] = a[(int64_t)k * n + j] / p;
+            d[(int64_t)k * n + j] = d[(int64_t)k * n + j] / p;
+        }
+        for (int i = 0; i < n; ++i) {                       /* eq. 15 */
+            if (i == k) continue;
+            double q = a[(int64_t)i * n + k];
+            for (int j = 0; j < n; ++j) {
+                a[(int64_t)i * n + j] = fma(-q, a[(int64_t)k * n + j], a[(int64_t)i * n + j]);
+                d[(int64_t)i * n + j] = fma(-q, d[(int64_t)k * n + j], d[(int64_t)i * n + j]);
+            }
+        }
+    }
+    for (int k = n - 1; k >= 0; --k) {                      /* A^-1 = Q D */
+        int c = jpiv[k];
+        if (c != k)
+            for (int j = 0; j < n; ++j) {
+                double t = d[(int64_t)k * n + j];
+                d[(int64_t)k * n + j] = d[(int64_t)c * n + j];
+                d[(int64_t)c * n + j] = t;
+            }
+    }
+    free(a);
+    res->code = ORA_OK;
+    res->rank = n;
+    res->det_sign = (m_acc < 0) ? -sign : sign;
+    res->det_mant = fabs(m_acc);
+    res->det_exp = e_acc;
+    res->det = ora_ldexp64((double)sign * m_acc, e_acc);
+    res->logabsdet = log(res->det_mant) + (double)e_acc * 0.69314718055994530942;
+    return ORA_OK;
+}
+
+/*
+ * Static-pivot FP64 LU determinant.  Applies, step by step, the row and
+ * column swaps of a previous full-pivot run (ipiv, jpiv: LAPACK xGETC2
+ * convention) and eliminates below the diagonal without searching:
+ * l = a_ik / a_kk, a_ij <- a_ij - l * a_kj (one fma).  det = sign * prod a_kk,
+ * kept as mantissa * 2^e like eq. 13's product.  A zero or non-finite pivot
+ * gives code SINGULAR / NONFINITE with rank k.
+ */
+int ora_lu_static_det_f64(int n, const double *A, int64_t lda, const int32_t *ipiv,
+                          const int32_t *jpiv, ora_result *res)
+{
+    double *a = (double *)malloc(sizeof(double) * (size_t)n * n);
+    if (!a) return -1;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) a[(int64_t)i * n + j] = A[(int64_t)i * lda + j];
+    int sign = 1;
+    double m_acc = 1.0;
+    int64_t e_acc = 0;
+    res->refine_iters = 0;
+    res->resid = NAN;
+    for (int k = 0; k < n; ++k) {
+        int r = ipiv[k], c = jpiv[k];
+        if (r != k) {
+            for (int j = 0; j < n; ++j) {
+                double t = a[(int64_t)k * n + j];
+                a[(int64_t)k * n + j] = a[(int64_t)r * n + j];
+                a[(int64_t)r * n + j] = t;
+            }
+            sign = -sign;
+        }
+        if (c != k) {
+            for (int i = 0; i < n; ++i) {
+                double t = a[(int64_t)i * n + k];
+                a[(int64_t)i * n + k] = a[(int64_t)i * n + c];
+                a[(int64_t)i * n + c] = t;
+            }
+            sign = -sign;
+        }
+        double p = a[(int64_t)k * n + k];
+        if (!isfinite(p)) {
+            ora_fill_failure(res, ORA_NONFINITE, k, n, NULL, NULL);
+            free(a);
+            return ORA_NONFINITE;
+        }
+        if (p == 0.0) {
+            ora_fill_failure(res, ORA_SINGULAR, k, n, NULL, NULL);
+            free(a);
+            return ORA_SINGULAR;
+        }
+        int e1, e2;
+        double f = frexp(p, &e1);
+        m_acc = m_acc * f;
+        e_acc += e1;
+        m_acc = frexp(m_acc, &e2);
+        e_acc += e2;
+        for (int i = k + 1; i < n; ++i) {
+            double l = a[(int64_t)i * n + k] / p;
+            for (int j = k + 1; j < n; ++j)
+                a[(int64_t)i * n + j] = fma(-l, a[(int64_t)k * n + j], a[(int64_t)i * n + j]);
+        }
+    }
+    free(a);
+    res->code = ORA_OK;
+    res->rank = n;
+    res->det_sign = (m_acc < 0) ? -sign : sign;
+    res->det_mant = fabs(m_acc);
+    res->det_exp = e_acc;
+    res->det = ora_ldexp64((double)sign * m_acc, e_acc);
+    res->logabsdet = log(res->det_mant) + (double)e_acc * 0.69314718055994530942;
+    return ORA_OK;
+}
+
+/* Size of the record, so the Python side can check its layout. */
+int ora_result_size(void) { return (int)sizeof(ora_result); }

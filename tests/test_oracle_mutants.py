@@ -1,0 +1,118 @@
+"""Planted mistakes: each mutant is a copy of the oracle's C source with one
+plausible error (a flipped sign, a dropped term, a wrong index, a transposed
+operand, a different tie-break or pivot rule), compiled on the CPU.  The pin
+battery below -- the same kinds of check as test_oracle_pins.py -- must
+reject every one of them, which shows the pins can tell a wrong oracle from
+the right one.  The product library is not involved."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_7962_amd import inputs
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "gj_oracle.c")
+
+MUTANTS = {
+    "tie_break_last_max": ("if (v > best) { best = v; r = i; c = j; }",
+                           "if (v >= best) { best = v; r = i; c = j; }"),
+    "eq15_sign": ("W[(int64_t)i * n + j] = FMA(-q,", "W[(int64_t)i * n + j] = FMA(q,"),
+    "eq15_transposed": ("FMA(-q, W[(int64_t)k * n + j],", "FMA(-q, W[(int64_t)j * n + k],"),
+    "pivot_column_not_cleared": ("W[(int64_t)i * n + k] = (T)0;", "(void)0;"),
+    "pivot_slot_not_one": ("W[(int64_t)k * n + k] = (T)1;", "(void)0;"),
+    "unscramble_roles_swapped": ("int r = ipiv[k], c = jpiv[k];", "int r = jpiv[k], c = ipiv[k];"),
+    "det_sign_flipped": ("res->det_sign = (m_acc < 0) ? -sign : sign;",
+                         "res->det_sign = (m_acc < 0) ? sign : -sign;"),
+    "partial_pivoting": ("for (int j = k; j < n; ++j) {", "for (int j = k; j <= k; ++j) {"),
+    "search_includes_done_rows": ("for (int i = k; i < n; ++i)                                                \\",
+                                  "for (int i = 0; i < n; ++i)                                                \\"),
+    "no_zero_test": ("if (best == (T)0 || best < tau) {", "if (best < tau) {"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert old in src, f"mutation anchor for {name} not found"
+    mutated = src.replace(old, new)
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(mutated)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-o", str(so), str(c), "-lm"], check=True)
+    lib = ctypes.CDLL(str(so))
+    fn = lib.ora_gj_invert_f64
+    P = ctypes.c_void_p
+    fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P, P, P,
+                   ctypes.POINTER(oracle.OraResult)]
+    return fn
+
+
+def _invert(fn, A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    X = np.empty_like(A)
+    ipiv = np.full(n, -1, np.int32)
+    jpiv = np.full(n, -1, np.int32)
+    res = oracle.OraResult()
+    fn(n, A.ctypes.data_as(ctypes.c_void_p), n, -1.0, X.ctypes.data_as(ctypes.c_void_p),
+       ipiv.ctypes.data_as(ctypes.c_void_p), jpiv.ctypes.data_as(ctypes.c_void_p),
+       ctypes.byref(res))
+    return X, ipiv, jpiv, res.as_dict()
+
+
+def _pin_battery(fn):
+    """Returns the list of pins that fail."""
+    failed = []
+    with np.errstate(all="ignore"):
+        P = inputs.pascal(3)
+        X, ipiv, jpiv, res = _invert(fn, P)
+        if not (np.array_equal(np.rint(X), [[3, -3, 1], [-3, 5, -2], [1, -2, 1]])
+                and ipiv.tolist() == [2, 2, 2] and jpiv.tolist() == [2, 2, 2]
+                and res["det_sign"] == 1):
+            failed.append("pascal3")
+        H = inputs.sylvester_hadamard(8)
+        X, ipiv, jpiv, res = _invert(fn, H)
+        if not (np.array_equal(X, H.T / 8) and ipiv.tolist() == list(range(8))):
+            failed.append("hadamard8")
+        s = [2, 0, 3, 1]
+        Pm = np.zeros((4, 4))
+        Pm[np.arange(4), s] = 1
+        X, ipiv, jpiv, res = _invert(fn, Pm)
+        if not (np.array_equal(X, Pm.T) and res["det"] == -1 and jpiv.tolist() == [2, 2, 3, 3]):
+            failed.append("permutation")
+        X, ipiv, jpiv, res = _invert(fn, np.zeros((3, 3)))
+        if not (res["code"] == 1 and res["rank"] == 0):
+            failed.append("zero_matrix")
+        from scipy.linalg import lapack
+        rng = inputs.rng_for(0, 77)
+        for t in range(5):
+            n = int(rng.integers(3, 16))
+            A = rng.standard_normal((n, n))
+            X, ipiv, jpiv, res = _invert(fn, A)
+            _, il, jl, _ = lapack.dgetc2(A)
+            if not (np.isfinite(X).all() and oracle.residual(A, X) <= 10 * n * 2.0 ** -53):
+                failed.append(f"residual{t}")
+                break
+            if not (np.array_equal(ipiv, il) and np.array_equal(jpiv, jl)):
+                failed.append(f"dgetc2_{t}")
+                break
+            if res["det_sign"] != np.linalg.slogdet(A)[0]:
+                failed.append(f"det_sign{t}")
+                break
+    return failed
+
+
+def test_unmutated_source_passes_battery(tmp_path):
+    fn = _build(tmp_path, "identity", "#include <math.h>", "#include <math.h>")
+    assert _pin_battery(fn) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    fn = _build(tmp_path, name, old, new)
+    failed = _pin_battery(fn)
+    assert failed, f"mutant {name} passed every pin"

@@ -1,0 +1,286 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own code (worked examples, closed forms,
+exact arithmetic, invariants, brute force, a LAPACK routine, higher
+precision).  CPU only."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_7962_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U64 = 2.0 ** -53
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- worked cases
+
+def test_pascal3_default_matrix():
+    g = _golden("pascal3.json")
+    A = np.array(g["A"], dtype=np.float64)
+    X, ipiv, jpiv, res = oracle.gj_invert_f64(A)
+    assert res["code"] == 0 and res["rank"] == 3
+    assert ipiv.tolist() == g["ipiv"] and jpiv.tolist() == g["jpiv"]
+    assert res["det_sign"] == g["det_sign"]
+    # exact integers in rational arithmetic; allow rounding in FP64
+    assert np.array_equal(np.rint(X), np.array(g["inverse"], dtype=np.float64))
+    assert np.max(np.abs(X - np.array(g["inverse"]))) <= 1e-14
+    assert abs(res["det"] - g["det"]) <= 1e-14
+    # the product of the printed pivots is the determinant (eq. 13)
+    assert abs(np.prod(g["pivots"]) - res["det"]) <= 1e-15
+
+
+@pytest.mark.parametrize("case", _golden("small_cases.json")["cases"], ids=lambda c: c["name"])
+def test_exact_small_cases(case):
+    A = np.array(case["A"], dtype=np.float64)
+    X, ipiv, jpiv, res = oracle.gj_invert_f64(A)
+    assert res["code"] == case["code"]
+    assert res["rank"] == case["rank"]
+    assert ipiv.tolist() == case["ipiv"] and jpiv.tolist() == case["jpiv"]
+    if case["code"] == 0:
+        assert np.array_equal(X, np.array(case["inverse"], dtype=np.float64))
+        assert res["det"] == case["det"]
+    else:
+        assert np.isnan(X).all()
+        assert res["det_sign"] == 0 and res["det"] == 0.0
+        assert res["logabsdet"] == -math.inf
+
+
+def _pascal_inverse_exact(n):
+    """P = L L^T with L_ij = C(i,j); (L^-1)_ij = (-1)^(i-j) C(i,j)."""
+    Li = [[(-1) ** (i - j) * math.comb(i, j) if j <= i else 0 for j in range(n)] for i in range(n)]
+    return [[sum(Li[k][i] * Li[k][j] for k in range(n)) for j in range(n)] for i in range(n)]
+
+
+@pytest.mark.parametrize("n", range(1, 10))
+def test_pascal_closed_form(n):
+    A = inputs.pascal(n)
+    X, _, _, res = oracle.gj_invert_f64(A)
+    exact = np.array(_pascal_inverse_exact(n), dtype=np.float64)
+    assert np.array_equal(np.rint(X), exact)
+    cond = np.linalg.cond(A)
+    assert np.max(np.abs(X - exact)) <= 8 * n * cond * U64 * np.max(np.abs(exact))
+    assert abs(res["det"] - 1.0) <= 8 * n * cond * U64
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 32, 64])
+def test_hadamard_exact_and_ties(n):
+    """Every |a| ties at every step: the tie-break picks (k,k), no swaps, and
+    all arithmetic is exact, so X == H^T / n bit for bit and det = +-n^(n/2)."""
+    H = inputs.sylvester_hadamard(n)
+    X, ipiv, jpiv, res = oracle.gj_invert_f64(H)
+    assert np.array_equal(X, H.T / n)
+    assert ipiv.tolist() == list(range(n)) and jpiv.tolist() == list(range(n))
+    m = int(round(math.log2(n)))
+    # n^(n/2) = 2^(m n / 2) = 0.5 * 2^(m n/2 + 1)
+    assert res["det_mant"] == 0.5 and res["det_exp"] == m * n // 2 + 1
+    assert res["det_sign"] == (-1 if n == 2 else 1)
+
+
+@pytest.mark.parametrize("n", [4, 8, 16, 32, 64])
+def test_hadamard_exactly_singular(n):
+    H = inputs.sylvester_hadamard(n)
+    A = H.copy()
+    A[:, n - 1] = H[:, 0] + H[:, 1]
+    _, ipiv, _, res = oracle.gj_invert_f64(A)
+    assert res["code"] == 1 and res["rank"] == n - 1 and ipiv[n - 1] == -1
+    B = H.copy()
+    B[n - 1] = H[0]
+    _, _, _, res = oracle.gj_invert_f64(B)
+    assert res["code"] == 1 and res["rank"] == n - 1
+
+
+def test_closed_form_n1_n2():
+    for a in (3.0, -0.125, 7.5e-300, 1e300):
+        X, _, _, res = oracle.gj_invert_f64(np.array([[a]]))
+        assert X[0, 0] == 1.0 / a and res["det"] == a
+    rng = inputs.rng_for(0, 101)
+    for _ in range(200):
+        A = rng.standard_normal((2, 2))
+        a, b, c, d = A.ravel()
+        det = a * d - b * c
+        exact = np.array([[d, -b], [-c, a]]) / det
+        X, _, _, res = oracle.gj_invert_f64(A)
+        cond = np.linalg.cond(A)
+        assert np.max(np.abs(X - exact)) <= 8 * cond * U64 * np.max(np.abs(exact))
+        assert abs(res["det"] - det) <= 8 * cond * U64 * abs(det)
+
+
+# ----------------------------------------------------------------- invariants
+
+@pytest.mark.parametrize("seed", range(6))
+def test_power_of_two_scaling_is_bitwise(seed):
+    rng = inputs.rng_for(0, 200 + seed)
+    n = int(rng.integers(2, 20))
+    A = rng.standard_normal((n, n))
+    s = int(rng.integers(-20, 20))
+    X, ipiv, jpiv, res = oracle.gj_invert_f64(A)
+    Xs, ipiv_s, jpiv_s, res_s = oracle.gj_invert_f64(np.ldexp(A, s))
+    assert np.array_equal(Xs, np.ldexp(X, -s))
+    assert np.array_equal(ipiv, ipiv_s) and np.array_equal(jpiv, jpiv_s)
+    assert res_s["det_mant"] == res["det_mant"] and res_s["det_exp"] == res["det_exp"] + s * n
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_permutation_equivariance_is_bitwise(seed):
+    """Full pivoting picks the same elements whatever the row/column order
+    (tie-free input), so inv(A[p][:,q]) == inv(A)[q][:,p] exactly."""
+    rng = inputs.rng_for(0, 300 + seed)
+    n = int(rng.integers(2, 24))
+    A = rng.standard_normal((n, n))
+    p, q = rng.permutation(n), rng.permutation(n)
+    X, _, _, res = oracle.gj_invert_f64(A)
+    Xp, _, _, res_p = oracle.gj_invert_f64(A[p][:, q])
+    assert np.array_equal(Xp, X[q][:, p])
+    assert res_p["det_mant"] == res["det_mant"] and res_p["det_exp"] == res["det_exp"]
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 6])
+def test_cofactor_determinant(n):
+    rng = inputs.rng_for(0, 400 + n)
+    for _ in range(3):
+        A = rng.standard_normal((n, n))
+        exact = oracle.cofactor_det(A)
+        _, _, _, res = oracle.gj_invert_f64(A)
+        cond = np.linalg.cond(A)
+        rel = abs(Fraction(res["det"]) - exact) / abs(exact)
+        assert float(rel) <= 16 * n * cond * U64
+        assert res["det_sign"] == (1 if exact > 0 else -1)
+
+
+@pytest.mark.parametrize("n", [5, 17, 64, 130])
+def test_residual_bound(n):
+    A = inputs.rng_for(0, 500 + n).standard_normal((n, n))
+    X, _, _, res = oracle.gj_invert_f64(A)
+    assert oracle.residual(A, X) <= 10 * n * U64
+
+
+def test_lapack_complete_pivoting_sequence():
+    """LAPACK dgetc2 (complete-pivot LU) chooses the same pivots as GJ with full
+    pivoting on tie-free inputs: both search the same trailing block, whose
+    entries agree to rounding."""
+    from scipy.linalg import lapack
+    rng = inputs.rng_for(0, 600)
+    for _ in range(40):
+        n = int(rng.integers(1, 24))
+        A = rng.standard_normal((n, n))
+        _, ipiv_l, jpiv_l, info = lapack.dgetc2(A)
+        _, ipiv, jpiv, res = oracle.gj_invert_f64(A)
+        assert info == 0
+        assert np.array_equal(ipiv, ipiv_l) and np.array_equal(jpiv, jpiv_l)
+        sign, logdet = np.linalg.slogdet(A)
+        assert res["det_sign"] == sign
+        assert abs(res["logabsdet"] - logdet) <= 1e-12 * max(1.0, abs(logdet))
+
+
+def test_augmented_form_is_bitwise_equal():
+    """The in-place array and the literal [A|D] form of eqs. 14-15 agree bit
+    for bit (the structural zeros and ones of D do not change any value)."""
+    rng = inputs.rng_for(0, 700)
+    for _ in range(30):
+        n = int(rng.integers(1, 20))
+        A = rng.standard_normal((n, n))
+        X, ipiv, jpiv, res = oracle.gj_invert_f64(A)
+        X2, ipiv2, jpiv2, res2 = oracle.gj_augmented_f64(A)
+        assert X.tobytes() == X2.tobytes()
+        assert np.array_equal(ipiv, ipiv2) and np.array_equal(jpiv, jpiv2)
+        assert res["det_mant"] == res2["det_mant"] and res["det_exp"] == res2["det_exp"]
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
+def test_forward_error_against_long_double(cond):
+    n = 48
+    A = inputs.conditioned(n, cond, inputs.rng_for(0, 800))
+    X, ipiv, jpiv, _ = oracle.gj_invert_f64(A)
+    Xt, ipiv_t, jpiv_t, _ = oracle.gj_invert_f80(A)
+    err = np.linalg.norm(X - Xt) / np.linalg.norm(Xt)
+    assert err <= 4 * n * cond * U64
+    # the long double run itself is far more accurate: compare with scipy's inverse
+    assert np.linalg.norm(Xt - np.linalg.inv(A)) / np.linalg.norm(Xt) <= 8 * n * cond * U64
+
+
+def test_float_model_matches_its_precision():
+    A = inputs.conditioned(40, 1e3, inputs.rng_for(0, 900))
+    X32, _, _, res = oracle.gj_invert_f32(A.astype(np.float32))
+    assert X32.dtype == np.float32 and res["code"] == 0
+    r = oracle.residual(A.astype(np.float32).astype(np.float64), X32)
+    assert r <= 10 * 40 * 2.0 ** -24
+
+
+def test_nonfinite_and_threshold():
+    A = np.eye(4)
+    A[2, 1] = np.nan
+    X, ipiv, _, res = oracle.gj_invert_f64(A)
+    assert res["code"] == 2 and res["rank"] == 0 and np.isnan(X).all() and ipiv[0] == -1
+    A = np.eye(4)
+    A[3, 0] = np.inf
+    assert oracle.gj_invert_f64(A)[3]["code"] == 2
+    # tiny but non-zero pivot: singular under the default threshold, not under tau = 0
+    B = np.diag([1.0, 1.0, 1.0, 1e-17])
+    assert oracle.gj_invert_f64(B)[3]["code"] == 1
+    X, _, _, res = oracle.gj_invert_f64(B, zero_tol=0.0)
+    assert res["code"] == 0 and X[3, 3] == 1e17
+
+
+def test_lu_static_det_agrees():
+    rng = inputs.rng_for(0, 1000)
+    for _ in range(10):
+        n = int(rng.integers(2, 40))
+        A = rng.standard_normal((n, n))
+        _, ipiv, jpiv, res = oracle.gj_invert_f64(A)
+        lu = oracle.lu_static_det_f64(A, ipiv, jpiv)
+        assert lu["det_sign"] == res["det_sign"]
+        assert abs(lu["logabsdet"] - res["logabsdet"]) <= 1e-12 * max(1.0, abs(res["logabsdet"]))
+    # exact on a diagonal matrix with swaps
+    D = np.diag([2.0, -5.0, 0.5, 5.0])
+    lu = oracle.lu_static_det_f64(D, [1, 3, 3, 3], [1, 3, 3, 3])
+    assert lu["det"] == -25.0
+
+
+def test_conditioned_generator_closed_form_logdet():
+    n, cond = 64, 1e6
+    A = inputs.conditioned(n, cond, inputs.rng_for(0, 1100))
+    _, _, _, res = oracle.gj_invert_f64(A)
+    assert res["det_sign"] == 1
+    assert abs(res["logabsdet"] - inputs.closed_form_logdet(n, cond)) <= 1e-9 * n * math.log(cond)
+
+
+@pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
+def test_newton_schulz_squares_the_residual(cond):
+    """One update maps R to R^2 (X' = X + X R gives I - A X' = R^2), and the
+    iteration from an FP32 inverse reaches the FP64 oracle's accuracy."""
+    n = 64
+    A = inputs.conditioned(n, cond, inputs.rng_for(0, 1200))
+    X32, _, _, _ = oracle.gj_invert_f32(A.astype(np.float32))
+    X0 = X32.astype(np.float64)
+    R0 = np.eye(n) - A @ X0
+    X1 = X0 + X0 @ R0
+    R1 = np.eye(n) - A @ X1
+    assert np.linalg.norm(R1 - R0 @ R0) <= 64 * n * U64 * np.linalg.norm(A) * np.linalg.norm(X1)
+    X, updates, norms, accepted = oracle.newton_schulz(A, X0)
+    assert accepted and 1 <= updates <= 6
+    Xt, _, _, _ = oracle.gj_invert_f80(A)
+    Xo, _, _, _ = oracle.gj_invert_f64(A)
+    err_ns = np.linalg.norm(X - Xt) / np.linalg.norm(Xt)
+    err_or = np.linalg.norm(Xo - Xt) / np.linalg.norm(Xt)
+    assert err_ns <= 2 * max(err_or, 1e-14)
+
+
+def test_pivots_to_permutations():
+    A = inputs.rng_for(0, 1300).standard_normal((12, 12))
+    X, ipiv, jpiv, _ = oracle.gj_invert_f64(A)
+    rows, cols = oracle.perms_from_pivots(ipiv, jpiv)
+    B = A[rows][:, cols]
+    # after the permutation, no search is needed: the diagonal is the pivot order
+    Xb, ipiv_b, jpiv_b, _ = oracle.gj_invert_f64(B)
+    assert ipiv_b.tolist() == list(range(12)) and jpiv_b.tolist() == list(range(12))
+    assert np.array_equal(Xb, X[cols][:, rows])
