@@ -1,0 +1,186 @@
+/*
+ * gj.h -- C ABI of libgj: Gauss-Jordan matrix inversion with full pivoting on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: C. V. Anghel Drugarin, "Numerical application and Turbo C program
+ * using the Gauss-Jordan method" (arXiv:1401.7962), section 2:
+ *   - A^0 = A, D^0 = I (eqs. 1-2); n steps; A^n = I and A^-1 = D^n (eqs. 11-12);
+ *   - at each step the element of largest |a| in the trailing block is brought
+ *     to the pivot position by swapping rows k,i and columns k,j (Obs. 2-3);
+ *   - the pivot rows of A and D are divided by the pivot (eq. 14) and every
+ *     other row i receives -a_ik times the new pivot row (eq. 15);
+ *   - det A is the product of the pivots (eq. 13);
+ *   - a pivot that is null or below a preset zero threshold, with no other
+ *     candidate left, means A is singular (Obs. 2);
+ *   - the swaps are undone in reverse order at the end (Obs. 3, conclusions).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller.  The
+ *   library allocates nothing per call and keeps no pointer after the work it
+ *   enqueued has finished.  Scratch space is the caller's workspace `ws` of
+ *   `ws_bytes` bytes (at least gj_workspace_size(...), 256-byte aligned).
+ * Layout.  Row-major, leading dimension >= n, in elements.  A is never
+ *   written; X must not overlap A or the workspace.
+ * Stream.  `stream` is a hipStream_t (NULL = the null stream).  Every call
+ *   enqueues its kernels on it and returns; results are valid once the stream
+ *   has been synchronised.  The return value covers only argument checks and
+ *   launch errors; numeric outcomes (singular, non-finite) are reported per
+ *   matrix in the device-side gj_result.
+ * Pivots.  0-based, LAPACK xGETC2 convention: at step k rows k <-> ipiv[k] and
+ *   columns k <-> jpiv[k] of the current (already swapped) matrix were
+ *   exchanged.  Ties between equal |a| go to the lowest row, then the lowest
+ *   column, of the current matrix.  Steps not taken hold -1.
+ * Determinant.  Kept exactly as det_sign * det_mant * 2^det_exp with det_mant
+ *   in [0.5, 1): the product of pivots in step order, renormalised after every
+ *   multiplication, so it neither overflows nor underflows.
+ * Errors.  No C++ exception crosses this boundary.  A singular matrix is not an
+ *   error: the call returns GJ_OK and the matrix's gj_result says SINGULAR.
+ * Threads.  Library state is read-only after load, so calls on different
+ *   streams with different workspaces may run concurrently.
+ */
+#ifndef GJ_H
+#define GJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes of the entry points (synchronous checks and launches). */
+typedef enum {
+    GJ_OK = 0,
+    GJ_E_INVALID_ARG = -1,  /* n < 1, ld < n, NULL pointer, overlap, bad option */
+    GJ_E_WORKSPACE = -2,    /* ws_bytes smaller than gj_workspace_size() or misaligned */
+    GJ_E_HIP = -3,          /* a HIP runtime call or launch failed */
+    GJ_E_UNSUPPORTED = -4   /* size or option outside what this build handles */
+} gj_status;
+
+/* Per-matrix outcome (gj_result.code). */
+enum {
+    GJ_RES_OK = 0,
+    GJ_RES_SINGULAR = 1,        /* every candidate pivot was 0 or below the zero threshold */
+    GJ_RES_NONFINITE = 2,       /* a NaN or infinity appeared among the candidates */
+    GJ_RES_REFINE_FALLBACK = 3  /* refined path: refinement did not converge; the plain
+                                   FP64 elimination produced the result instead */
+};
+
+/* gj_opts.precision */
+enum {
+    GJ_PREC_FP64 = 0,          /* FP64 elimination; bit-exact with the reference order */
+    GJ_PREC_FP32_REFINED = 1   /* FP32 elimination, FP64 Newton-Schulz refinement
+                                  X <- X + X (I - A X), FP64 determinant */
+};
+
+/* gj_opts.flags */
+enum {
+    GJ_FLAG_REUSE_PLAN = 1  /* gj_invert_batched: the workspace already holds the plan that
+                               an earlier call with the same n_host / off_host / piv_off_host
+                               and workspace uploaded; skip the upload (and the stream
+                               synchronisation it needs), e.g. while capturing a HIP graph */
+};
+
+/* gj_workspace_size op codes */
+enum { GJ_OP_INVERT = 0, GJ_OP_DET = 1, GJ_OP_INVERT_BATCHED = 2 };
+
+/* Per-matrix result, written to device memory by every entry point. */
+typedef struct gj_result {
+    int32_t code;          /* GJ_RES_* */
+    int32_t rank;          /* pivot steps completed (n when OK) */
+    int32_t det_sign;      /* -1 or +1; 0 when singular or non-finite */
+    int32_t refine_iters;  /* Newton-Schulz updates applied (refined path), else 0 */
+    double det_mant;       /* |det| = det_mant * 2^det_exp, det_mant in [0.5, 1) */
+    int64_t det_exp;
+    double det;            /* det as a double (may overflow to +-inf or underflow to 0) */
+    double logabsdet;      /* ln|det| (-inf when singular) */
+    double resid;          /* ||A X - I||_F / (||A||_F ||X||_F) if requested, else NaN */
+} gj_result;
+
+/* Options; pass NULL for the defaults shown. */
+typedef struct gj_opts {
+    int32_t precision;        /* GJ_PREC_FP64 */
+    int32_t want_resid;       /* 0; 1 = compute gj_result.resid (one extra FP64 product) */
+    int32_t max_refine_iters; /* 10; refined path: at most this many Newton-Schulz updates */
+    int32_t flags;            /* 0; GJ_FLAG_* bits */
+    double zero_tol;          /* -1; < 0 selects tau = n * 2^-52 * max|a_ij| (FP64
+                                 elimination) and tau = 0 (FP32 elimination); >= 0 is
+                                 used as given.  A step is singular when its best
+                                 candidate m satisfies m == 0 or m < tau (Obs. 2). */
+    void *step_events[2];     /* NULL; optional hipEvent_t pair recorded on `stream`
+                                 just before the first and just after the last
+                                 elimination-step kernel (used for timing) */
+} gj_opts;
+
+/*
+ * gj_invert -- inverse, determinant and pivot sequence of one n x n matrix.
+ *   n          order, 1 <= n <= 16384
+ *   A, lda     input matrix (FP64), read only
+ *   X, ldx     output inverse (FP64); all NaN when the matrix is singular or
+ *              non-finite
+ *   ipiv, jpiv n int32 each: the pivot sequence (see Pivots above)
+ *   res        one gj_result
+ *   opts       NULL or options
+ *   ws         workspace of gj_workspace_size(GJ_OP_INVERT, n, NULL, opts) bytes
+ * Paper: eqs. 1-2, 11-15, Obs. 2-3.
+ */
+gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t ldx,
+                    int32_t *ipiv, int32_t *jpiv, gj_result *res, const gj_opts *opts,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * gj_invert_batched -- many independent matrices of uneven order in one call.
+ *   batch          number of matrices (>= 1)
+ *   n_host         HOST array [batch]: order of each matrix (1..16384)
+ *   off_host       HOST array [batch]: element offset of matrix b in A and in X;
+ *                  matrix b is A + off_host[b], row-major with ld = n_host[b]
+ *   A, X           packed device buffers (FP64); X regions must not overlap A
+ *   piv_off_host   HOST array [batch]: element offset of matrix b's pivots in
+ *                  ipiv / jpiv (n_host[b] entries each)
+ *   res            device array [batch] of gj_result
+ *   ws             workspace of gj_workspace_size(GJ_OP_INVERT_BATCHED, batch,
+ *                  n_host, opts) bytes
+ * The host arrays are read during the call only.  Matrices up to the on-chip
+ * limit are inverted one per workgroup (or one per wavefront) in a single
+ * persistent launch; larger ones go through the streaming path.
+ * Paper: as gj_invert, applied to each matrix.
+ */
+gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t *off_host,
+                            const double *A, double *X, const int64_t *piv_off_host,
+                            int32_t *ipiv, int32_t *jpiv, gj_result *res,
+                            const gj_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * gj_det -- determinant and pivot sequence only.  Runs the same elimination
+ * restricted to the rows still to be pivoted; the trailing-block values are
+ * produced by the identical operations, so the pivots and the determinant
+ * equal those of gj_invert bit for bit.  The inverse is not formed.
+ * Paper: eq. 13 and the conclusions (the determinant at no extra cost).
+ */
+gj_status gj_det(int32_t n, const double *A, int64_t lda, int32_t *ipiv, int32_t *jpiv,
+                 gj_result *res, const gj_opts *opts, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/*
+ * gj_workspace_size -- bytes of workspace needed.
+ *   op          GJ_OP_INVERT or GJ_OP_DET: n_or_batch = n, n_host unused;
+ *               GJ_OP_INVERT_BATCHED: n_or_batch = batch, n_host = HOST array of
+ *               orders.
+ * Returns 0 for invalid arguments.
+ */
+size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
+                         const gj_opts *opts);
+
+/* Text for a gj_status value or a GJ_RES_* code given as (100 + code). */
+const char *gj_status_string(int32_t code);
+
+/* Largest order handled on chip (one workgroup per matrix) for an elimination
+ * precision (GJ_PREC_FP64 or GJ_PREC_FP32_REFINED). */
+int32_t gj_onchip_max_n(int32_t precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GJ_H */

@@ -80,6 +80,11 @@ def _load():
             fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P, P, P,
                            ctypes.POINTER(OraResult)]
             fn.restype = ctypes.c_int
+        for name in ("ora_gj_invert_f64_first_steps", "ora_gj_invert_f32_first_steps"):
+            fn = getattr(lib, name)
+            fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P, P, P,
+                           ctypes.POINTER(OraResult), ctypes.c_int, P]
+            fn.restype = ctypes.c_int
         lib.ora_lu_static_det_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P,
                                               ctypes.POINTER(OraResult)]
         lib.ora_lu_static_det_f64.restype = ctypes.c_int
@@ -125,6 +130,25 @@ def gj_invert_f80(A, zero_tol: float = -1.0):
 def gj_augmented_f64(A, zero_tol: float = -1.0):
     """Literal eqs. 1-2, 14-15 on separate A and D arrays."""
     return _run("ora_gj_augmented_f64", A, zero_tol, np.float64, np.float64)
+
+
+def gj_first_steps(A, steps: int, zero_tol: float = -1.0, fp32: bool = False):
+    """Run only the first ``steps`` steps (same arithmetic as the full run).
+    Returns (ipiv, jpiv, pivot values, result dict); entries past the steps
+    taken are -1 / NaN.  Cost: steps * n^2 fma."""
+    dt = np.float32 if fp32 else np.float64
+    A = np.ascontiguousarray(A, dtype=dt)
+    n = A.shape[0]
+    X = np.empty((n, n), dtype=dt)
+    ipiv = np.full(n, -1, dtype=np.int32)
+    jpiv = np.full(n, -1, dtype=np.int32)
+    piv = np.full(n, np.nan)
+    res = OraResult()
+    name = "ora_gj_invert_f32_first_steps" if fp32 else "ora_gj_invert_f64_first_steps"
+    getattr(_load(), name)(n, _ptr(A), n, float(zero_tol), _ptr(X), _ptr(ipiv), _ptr(jpiv),
+                           ctypes.byref(res), int(steps), _ptr(piv))
+    k = min(int(steps), n)
+    return ipiv[:k], jpiv[:k], piv[:k], res.as_dict()
 
 
 def lu_static_det_f64(A, ipiv, jpiv) -> dict:

@@ -100,8 +100,25 @@ static void ora_fill_failure(ora_result *res, int code, int rank, int n,
  * Returns res->code.
  */
 #define GJ_INPLACE(NAME, T, FABS, FMA, FREXP, ISFIN, EPS_DEFAULT)                  \
+static int NAME##_run(int n, const T *A, int64_t lda, double zero_tol, T *X,       \
+                      int32_t *ipiv, int32_t *jpiv, ora_result *res,               \
+                      int max_steps, double *pivots);                              \
 int NAME(int n, const T *A, int64_t lda, double zero_tol, T *X,                    \
          int32_t *ipiv, int32_t *jpiv, ora_result *res)                            \
+{                                                                                  \
+    return NAME##_run(n, A, lda, zero_tol, X, ipiv, jpiv, res, n, NULL);           \
+}                                                                                  \
+/* the first max_steps steps only, recording each pivot value; the working  */   \
+/* array is left as it stands after those steps (no depivoting)             */   \
+int NAME##_first_steps(int n, const T *A, int64_t lda, double zero_tol, T *X,      \
+                       int32_t *ipiv, int32_t *jpiv, ora_result *res,              \
+                       int max_steps, double *pivots)                              \
+{                                                                                  \
+    return NAME##_run(n, A, lda, zero_tol, X, ipiv, jpiv, res, max_steps, pivots); \
+}                                                                                  \
+static int NAME##_run(int n, const T *A, int64_t lda, double zero_tol, T *X,       \
+                      int32_t *ipiv, int32_t *jpiv, ora_result *res,               \
+                      int max_steps, double *pivots)                               \
 {                                                                                  \
     T *W = X;                                   /* in-place working array */       \
     for (int i = 0; i < n; ++i)                                                    \
@@ -114,6 +131,7 @@ int NAME(int n, const T *A, int64_t lda, double zero_tol, T *X,                 
     res->refine_iters = 0;                                                         \
     res->resid = NAN;                                                              \
     for (int k = 0; k < n; ++k) {                                                  \
+        if (k == max_steps) return ORA_OK;                                         \
         /* pivot search over the trailing block, first maximum in row-major   */  \
         /* order (Obs. 2 and 3)                                               */  \
         T best = (T)-1;                                                            \
@@ -155,6 +173,7 @@ int NAME(int n, const T *A, int64_t lda, double zero_tol, T *X,                 
             sign = -sign;                                                          \
         }                                                                          \
         T p = W[(int64_t)k * n + k];                /* the pivot */                \
+        if (pivots) pivots[k] = (double)p;                                         \
         {   /* eq. 13: running product of pivots as mantissa * 2^e */              \
             int e1, e2;                                                            \
             T f = FREXP(p, &e1);                                                   \

@@ -1,0 +1,238 @@
+"""paper_1401_7962_amd -- full-pivot Gauss-Jordan inversion on MI355X.
+
+Thin Python binding over the C ABI of ``libgj.so`` (``include/gj.h``).  The
+functions here only marshal arguments: every step of the elimination runs in
+the library's HIP kernels.  PyTorch supplies device memory and the stream.
+If the library is missing, every call raises: there is no CPU fallback.
+
+Entry points (same names as the C ABI):
+    gj_invert, gj_invert_batched, gj_det, gj_workspace_size, gj_status_string,
+    gj_onchip_max_n
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgj.so")
+
+GJ_OK, GJ_E_INVALID_ARG, GJ_E_WORKSPACE, GJ_E_HIP, GJ_E_UNSUPPORTED = 0, -1, -2, -3, -4
+GJ_RES_OK, GJ_RES_SINGULAR, GJ_RES_NONFINITE, GJ_RES_REFINE_FALLBACK = 0, 1, 2, 3
+GJ_PREC_FP64, GJ_PREC_FP32_REFINED = 0, 1
+GJ_FLAG_REUSE_PLAN = 1
+GJ_OP_INVERT, GJ_OP_DET, GJ_OP_INVERT_BATCHED = 0, 1, 2
+
+
+class gj_result(ctypes.Structure):
+    _fields_ = [
+        ("code", ctypes.c_int32),
+        ("rank", ctypes.c_int32),
+        ("det_sign", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32),
+        ("det_mant", ctypes.c_double),
+        ("det_exp", ctypes.c_int64),
+        ("det", ctypes.c_double),
+        ("logabsdet", ctypes.c_double),
+        ("resid", ctypes.c_double),
+    ]
+
+
+RESULT_BYTES = ctypes.sizeof(gj_result)  # 56
+
+
+class gj_opts(ctypes.Structure):
+    _fields_ = [
+        ("precision", ctypes.c_int32),
+        ("want_resid", ctypes.c_int32),
+        ("max_refine_iters", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
+        ("zero_tol", ctypes.c_double),
+        ("step_events", ctypes.c_void_p * 2),
+    ]
+
+
+class GJError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgj.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise GJError(f"libgj.so not built ({path}); run __graft_entry__.build()")
+    import torch  # noqa: F401  -- make torch's HIP runtime the one the library binds to
+    lib = ctypes.CDLL(path)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    lib.gj_invert.argtypes = [I32, P, I64, P, I64, P, P, P, P, P, SZ, P]
+    lib.gj_invert.restype = I32
+    lib.gj_invert_batched.argtypes = [I32, P, P, P, P, P, P, P, P, P, P, SZ, P]
+    lib.gj_invert_batched.restype = I32
+    lib.gj_det.argtypes = [I32, P, I64, P, P, P, P, P, SZ, P]
+    lib.gj_det.restype = I32
+    lib.gj_workspace_size.argtypes = [I32, I32, P, P]
+    lib.gj_workspace_size.restype = SZ
+    lib.gj_status_string.argtypes = [I32]
+    lib.gj_status_string.restype = ctypes.c_char_p
+    lib.gj_onchip_max_n.argtypes = [I32]
+    lib.gj_onchip_max_n.restype = I32
+    _lib = lib
+    return lib
+
+
+EXPORTS = ("gj_invert", "gj_invert_batched", "gj_det", "gj_workspace_size",
+           "gj_status_string", "gj_onchip_max_n")
+
+
+def make_opts(precision=GJ_PREC_FP64, want_resid=False, max_refine_iters=10, flags=0,
+              zero_tol=-1.0, step_events=None) -> gj_opts:
+    o = gj_opts()
+    o.precision = precision
+    o.want_resid = 1 if want_resid else 0
+    o.max_refine_iters = max_refine_iters
+    o.flags = flags
+    o.zero_tol = zero_tol
+    if step_events is not None:
+        o.step_events[0] = step_events[0]
+        o.step_events[1] = step_events[1]
+    return o
+
+
+def _check(status: int):
+    if status != GJ_OK:
+        raise GJError(gj_status_string(status))
+
+
+def gj_status_string(code: int) -> str:
+    return load_library().gj_status_string(int(code)).decode()
+
+
+def gj_onchip_max_n(precision: int = GJ_PREC_FP64) -> int:
+    return int(load_library().gj_onchip_max_n(precision))
+
+
+def gj_workspace_size(op: int, n_or_batch: int, n_host=None, opts: gj_opts | None = None) -> int:
+    lib = load_library()
+    arr = None
+    if n_host is not None:
+        import numpy as np
+        arr = np.ascontiguousarray(n_host, dtype=np.int32)
+    return int(lib.gj_workspace_size(op, n_or_batch,
+                                      arr.ctypes.data_as(ctypes.c_void_p) if arr is not None else None,
+                                      ctypes.byref(opts) if opts is not None else None))
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _workspace(nbytes: int, device):
+    import torch
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def _res_tensor(count: int, device):
+    import torch
+    return torch.empty(count * RESULT_BYTES, dtype=torch.uint8, device=device)
+
+
+def results_to_dicts(res_tensor) -> list:
+    """Copy device gj_result records to the host as dicts."""
+    raw = res_tensor.detach().cpu().numpy().tobytes()
+    out = []
+    for i in range(len(raw) // RESULT_BYTES):
+        r = gj_result.from_buffer_copy(raw[i * RESULT_BYTES:(i + 1) * RESULT_BYTES])
+        out.append({name: getattr(r, name) for name, _ in gj_result._fields_})
+    return out
+
+
+def gj_invert(A, X=None, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = None, ws=None,
+              stream=None):
+    """Invert one square FP64 CUDA tensor.  Returns (X, ipiv, jpiv, res) where
+    res is the raw device record (use results_to_dicts)."""
+    import torch
+    lib = load_library()
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.float64 or not A.is_cuda:
+        raise GJError("A must be a square float64 CUDA tensor")
+    if A.stride(1) != 1:
+        raise GJError("A must be row-major (unit column stride)")
+    n = A.shape[0]
+    dev = A.device
+    X = torch.empty((n, n), dtype=torch.float64, device=dev) if X is None else X
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev) if ipiv is None else ipiv
+    jpiv = torch.empty(n, dtype=torch.int32, device=dev) if jpiv is None else jpiv
+    res = _res_tensor(1, dev) if res is None else res
+    need = gj_workspace_size(GJ_OP_INVERT, n, None, opts)
+    if ws is None:
+        ws = _workspace(need, dev)
+    st = lib.gj_invert(n, _ptr(A), A.stride(0), _ptr(X), X.stride(0), _ptr(ipiv), _ptr(jpiv),
+                       _ptr(res), ctypes.byref(opts) if opts is not None else None, _ptr(ws),
+                       ws.numel() * ws.element_size(), _stream_ptr(stream))
+    _check(st)
+    return X, ipiv, jpiv, res
+
+
+def gj_det(A, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = None, ws=None, stream=None):
+    import torch
+    lib = load_library()
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.float64 or not A.is_cuda:
+        raise GJError("A must be a square float64 CUDA tensor")
+    n = A.shape[0]
+    dev = A.device
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev) if ipiv is None else ipiv
+    jpiv = torch.empty(n, dtype=torch.int32, device=dev) if jpiv is None else jpiv
+    res = _res_tensor(1, dev) if res is None else res
+    need = gj_workspace_size(GJ_OP_DET, n, None, opts)
+    if ws is None:
+        ws = _workspace(need, dev)
+    st = lib.gj_det(n, _ptr(A), A.stride(0), _ptr(ipiv), _ptr(jpiv), _ptr(res),
+                    ctypes.byref(opts) if opts is not None else None, _ptr(ws),
+                    ws.numel() * ws.element_size(), _stream_ptr(stream))
+    _check(st)
+    return ipiv, jpiv, res
+
+
+def gj_invert_batched(sizes, offsets, A, X=None, piv_offsets=None, ipiv=None, jpiv=None, res=None,
+                      opts: gj_opts | None = None, ws=None, stream=None):
+    """Invert a packed batch.  ``sizes``/``offsets``/``piv_offsets`` are host
+    arrays; A (and X) are 1-D float64 CUDA tensors holding the members
+    row-major at the given element offsets."""
+    import numpy as np
+    import torch
+    lib = load_library()
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    batch = int(sizes.shape[0])
+    if piv_offsets is None:
+        piv_offsets = np.zeros(batch, dtype=np.int64)
+        piv_offsets[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
+    piv_offsets = np.ascontiguousarray(piv_offsets, dtype=np.int64)
+    dev = A.device
+    total_piv = int((piv_offsets + sizes).max())
+    X = torch.empty_like(A) if X is None else X
+    ipiv = torch.empty(total_piv, dtype=torch.int32, device=dev) if ipiv is None else ipiv
+    jpiv = torch.empty(total_piv, dtype=torch.int32, device=dev) if jpiv is None else jpiv
+    res = _res_tensor(batch, dev) if res is None else res
+    need = gj_workspace_size(GJ_OP_INVERT_BATCHED, batch, sizes, opts)
+    if need == 0:
+        raise GJError("invalid batch")
+    if ws is None:
+        ws = _workspace(need, dev)
+    st = lib.gj_invert_batched(batch, sizes.ctypes.data_as(ctypes.c_void_p),
+                               offsets.ctypes.data_as(ctypes.c_void_p), _ptr(A), _ptr(X),
+                               piv_offsets.ctypes.data_as(ctypes.c_void_p), _ptr(ipiv), _ptr(jpiv),
+                               _ptr(res), ctypes.byref(opts) if opts is not None else None, _ptr(ws),
+                               ws.numel() * ws.element_size(), _stream_ptr(stream))
+    _check(st)
+    return X, ipiv, jpiv, res, piv_offsets

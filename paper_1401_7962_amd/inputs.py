@@ -73,6 +73,8 @@ def batch_uneven(batch: int = 100_000, nmin: int = 8, nmax: int = 128,
     packed = rng.standard_normal(int(sq.sum()))
     for b in singular:
         n = int(sizes[b])
+        if n < 3:
+            continue          # too small to hold a column that is the sum of two others
         a, bb, c = rng.choice(n, 3, replace=False)
         M = packed[offs[b]: offs[b] + n * n].reshape(n, n)
         M[:, c] = M[:, a] + M[:, bb]

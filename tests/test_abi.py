@@ -1,0 +1,100 @@
+"""The C-ABI library loads and exports every function include/gj.h declares;
+argument checks reject bad calls before touching the GPU.  CPU only: no
+compute call is made here."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1401_7962_amd as gj
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "gj.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gj_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(gj.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return gj.load_library()
+
+
+def test_header_lists_the_boundary():
+    names = _header_functions()
+    for f in ("gj_invert", "gj_invert_batched", "gj_det", "gj_workspace_size", "gj_status_string"):
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", gj.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    for name in _header_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_result_and_opts_layout():
+    assert ctypes.sizeof(gj.gj_result) == 56
+    assert gj.gj_result.det_mant.offset == 16 and gj.gj_result.resid.offset == 48
+    assert ctypes.sizeof(gj.gj_opts) == 40
+
+
+def test_status_strings(lib):
+    for code in (0, -1, -2, -3, -4, 100, 101, 102, 103):
+        assert gj.gj_status_string(code)
+    assert gj.gj_status_string(-1).startswith("GJ_E_INVALID_ARG")
+
+
+def test_workspace_size(lib):
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 0) == 0
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 64) >= 256           # on chip: no real workspace
+    big = gj.gj_workspace_size(gj.GJ_OP_INVERT, 4096)
+    assert big >= 4096 * 4096 * 8                                     # holds the working array
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 20000) == 0         # beyond the supported order
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 3, [5, 200, 64]) > 200 * 200 * 8
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 0]) == 0
+    bad = gj.make_opts(precision=7)
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 64, None, bad) == 0
+
+
+def test_argument_checks_without_gpu(lib):
+    P = ctypes.c_void_p
+    fake = P(1 << 20)
+    # n < 1, lda < n, NULL pointers and bad options are rejected synchronously
+    assert lib.gj_invert(0, fake, 1, fake, 1, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    assert lib.gj_invert(4, fake, 3, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    assert lib.gj_invert(4, None, 4, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    o = gj.make_opts(flags=8)
+    assert lib.gj_invert(4, fake, 4, P(1 << 24), 4, fake, fake, fake, ctypes.byref(o), None, 0,
+                         None) == gj.GJ_E_INVALID_ARG
+    # X overlapping A
+    assert lib.gj_invert(4, fake, 4, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    # large n needs a workspace
+    assert lib.gj_invert(1000, P(1 << 30), 1000, P(1 << 40), 1000, fake, fake, fake, None, None, 0,
+                         None) == gj.GJ_E_WORKSPACE
+    assert lib.gj_det(0, fake, 1, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    n = np.array([4, 0], dtype=np.int32)
+    off = np.zeros(2, dtype=np.int64)
+    assert lib.gj_invert_batched(2, n.ctypes.data_as(P), off.ctypes.data_as(P), fake, P(1 << 24),
+                                 off.ctypes.data_as(P), fake, fake, fake, None, P(1 << 28), 1 << 20,
+                                 None) == gj.GJ_E_INVALID_ARG
+
+
+def test_binding_refuses_without_library(tmp_path):
+    with pytest.raises(gj.GJError):
+        gj._lib_saved = gj._lib
+        try:
+            gj._lib = None
+            gj.load_library(str(tmp_path / "missing.so"))
+        finally:
+            gj._lib = gj._lib_saved

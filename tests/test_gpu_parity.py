@@ -1,0 +1,169 @@
+"""GPU parity for the plain FP64 path: the HIP kernels against the FP64
+oracle, element by element.  The FP64 path performs exactly the oracle's
+operations (same division, one fma per element, same total-order pivot
+search), so the bar is bit-for-bit equality of X, the pivot sequence and the
+determinant's (sign, mantissa, exponent); log|det| within 4 ulp (device log).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_7962_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def gj():
+    import torch  # noqa: F401
+    import paper_1401_7962_amd as m
+    m.load_library()
+    return m
+
+
+def _dev(A):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(A, dtype=np.float64)).to("cuda")
+
+
+def _run_invert(gj, A, **kw):
+    import torch
+    opts = gj.make_opts(**kw) if kw else None
+    X, ipiv, jpiv, res = gj.gj_invert(_dev(A), opts=opts)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), ipiv.cpu().numpy(), jpiv.cpu().numpy(), gj.results_to_dicts(res)[0]
+
+
+def _assert_same(A, got, want, where=""):
+    X, ipiv, jpiv, r = got
+    Xo, io, jo, ro = want
+    assert r["code"] == ro["code"], where
+    assert r["rank"] == ro["rank"], where
+    assert np.array_equal(ipiv, io), where
+    assert np.array_equal(jpiv, jo), where
+    if ro["code"] == 0:
+        assert X.tobytes() == Xo.tobytes(), (where, np.max(np.abs(X - Xo)))
+        assert r["det_sign"] == ro["det_sign"], where
+        assert r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"], where
+        if np.isfinite(ro["det"]):
+            assert r["det"] == ro["det"], where
+        assert abs(r["logabsdet"] - ro["logabsdet"]) <= 4 * np.spacing(max(1.0, abs(ro["logabsdet"])))
+    else:
+        assert np.isnan(X).all(), where
+        assert r["det_sign"] == 0
+
+
+def test_pascal3_default_matrix(gj):
+    g = json.load(open(os.path.join(GOLDEN, "pascal3.json")))
+    A = np.array(g["A"], dtype=np.float64)
+    got = _run_invert(gj, A)
+    _assert_same(A, got, oracle.gj_invert_f64(A))
+    assert got[1].tolist() == g["ipiv"] and got[3]["det"] == 1.0
+
+
+def test_golden_small_cases(gj):
+    for case in json.load(open(os.path.join(GOLDEN, "small_cases.json")))["cases"]:
+        A = np.array(case["A"], dtype=np.float64)
+        got = _run_invert(gj, A)
+        _assert_same(A, got, oracle.gj_invert_f64(A), case["name"])
+        assert got[3]["code"] == case["code"] and got[1].tolist() == case["ipiv"]
+
+
+def test_single_normal_64(gj):
+    A = inputs.single_normal(64)
+    _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 9, 16, 17, 31, 32, 33, 63, 64, 65, 100, 127, 128])
+def test_onchip_sizes(gj, n):
+    A = inputs.rng_for(0, 2000 + n).standard_normal((n, n))
+    _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n}")
+
+
+@pytest.mark.parametrize("n", [129, 200, 257, 333, 512, 777, 1000])
+def test_streaming_sizes(gj, n):
+    A = inputs.rng_for(0, 3000 + n).standard_normal((n, n))
+    _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n}")
+
+
+@pytest.mark.parametrize("n", [4, 16, 64, 128, 256, 512])
+def test_hadamard_ties(gj, n):
+    """Every candidate ties at every step: the tie-break on the swapped
+    positions decides each pivot (virtual swaps on the streaming path)."""
+    H = inputs.sylvester_hadamard(n)
+    got = _run_invert(gj, H)
+    _assert_same(H, got, oracle.gj_invert_f64(H), f"H{n}")
+    assert np.array_equal(got[0], H.T / n)
+
+
+@pytest.mark.parametrize("n", [16, 128, 256])
+def test_exactly_singular(gj, n):
+    H = inputs.sylvester_hadamard(n)
+    A = H.copy()
+    A[:, n - 1] = H[:, 0] + H[:, 1]
+    got = _run_invert(gj, A)
+    _assert_same(A, got, oracle.gj_invert_f64(A), f"singular H{n}")
+    assert got[3]["code"] == 1 and got[3]["rank"] == n - 1
+
+
+@pytest.mark.parametrize("n", [20, 300])
+def test_nonfinite(gj, n):
+    A = inputs.rng_for(0, 4000 + n).standard_normal((n, n))
+    A[n // 2, n // 3] = np.nan
+    got = _run_invert(gj, A)
+    _assert_same(A, got, oracle.gj_invert_f64(A), "nan")
+    assert got[3]["code"] == 2
+    B = inputs.rng_for(0, 4100 + n).standard_normal((n, n))
+    B[1, 2] = np.inf
+    got = _run_invert(gj, B)
+    assert got[3]["code"] == 2
+
+
+@pytest.mark.parametrize("n", [40, 260])
+def test_zero_threshold(gj, n):
+    A = inputs.rng_for(0, 4200 + n).standard_normal((n, n))
+    A[:, 5] = A[:, 1] * 0.5 + A[:, 2] * 0.25 + 1e-15 * A[:, 3]   # nearly rank-deficient
+    for tol in (-1.0, 0.0, 1e-3):
+        got = _run_invert(gj, A, zero_tol=tol)
+        _assert_same(A, got, oracle.gj_invert_f64(A, zero_tol=tol), f"tol={tol}")
+
+
+@pytest.mark.parametrize("n", [50, 128, 300])
+def test_det_matches_invert(gj, n):
+    import torch
+    A = inputs.rng_for(0, 4300 + n).standard_normal((n, n))
+    ipiv, jpiv, res = gj.gj_det(_dev(A))
+    torch.cuda.synchronize()
+    r = gj.results_to_dicts(res)[0]
+    _, io, jo, ro = oracle.gj_invert_f64(A)
+    assert np.array_equal(ipiv.cpu().numpy(), io) and np.array_equal(jpiv.cpu().numpy(), jo)
+    assert r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"]
+    assert r["det_sign"] == ro["det_sign"]
+
+
+def test_batched_mixed(gj):
+    """A packed batch spanning the wavefront, workgroup and streaming paths,
+    with planted rank-(n-1) members."""
+    import torch
+    sizes, offs, packed, singular = inputs.batch_uneven(batch=240, nmin=1, nmax=300,
+                                                        singular_frac=0.05, offset=77)
+    A = torch.from_numpy(packed).to("cuda")
+    X, ipiv, jpiv, res, poff = gj.gj_invert_batched(sizes, offs, A)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    ih, jh = ipiv.cpu().numpy(), jpiv.cpu().numpy()
+    rs = gj.results_to_dicts(res)
+    n_sing = 0
+    for b in range(len(sizes)):
+        n = int(sizes[b])
+        Ab = packed[offs[b]:offs[b] + n * n].reshape(n, n)
+        got = (Xh[offs[b]:offs[b] + n * n].reshape(n, n), ih[poff[b]:poff[b] + n],
+               jh[poff[b]:poff[b] + n], rs[b])
+        _assert_same(Ab, got, oracle.gj_invert_f64(Ab), f"member {b} n={n}")
+        n_sing += rs[b]["code"] == 1
+    assert n_sing >= len(singular) - 2   # tiny members (n < 3) cannot host the planted sum
