@@ -172,6 +172,20 @@ gj_status gj_det(int32_t n, const double *A, int64_t lda, int32_t *ipiv, int32_t
 size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
                          const gj_opts *opts);
 
+/*
+ * gj_dgemm -- the FP64 matrix-core product used by the refinement and by the
+ * FP64 determinant of the refined path:
+ *     D = alpha * (A B) + beta * C + gamma * I       (row-major, FP64)
+ * A is M x K (lda), B is K x N (ldb), C and D are M x N (ldc, ldd); C may be
+ * NULL when beta == 0 and may equal D (in-place update).  gamma adds to the
+ * entries with row == column.  Device pointers; asynchronous on `stream`.
+ * Paper: not in the paper; the Newton-Schulz step X <- X + X (I - A X) of
+ * the refined path is built from two of these products.
+ */
+gj_status gj_dgemm(int32_t M, int32_t N, int32_t K, double alpha, const double *A, int64_t lda,
+                   const double *B, int64_t ldb, double beta, const double *C, int64_t ldc,
+                   double gamma, double *D, int64_t ldd, void *stream);
+
 /* Text for a gj_status value or a GJ_RES_* code given as (100 + code). */
 const char *gj_status_string(int32_t code);
 

@@ -178,15 +178,16 @@ def residual(A, X) -> float:
     return float(np.linalg.norm(R) / (np.linalg.norm(A) * np.linalg.norm(X)))
 
 
-def newton_schulz(A, X0, max_iters: int = 10, stall: float = 0.5, accept: float = 1e-6):
+def newton_schulz(A, X0, max_iters: int = 10, stall: float = 0.5, accept: float = 1e-2):
     """Newton-Schulz refinement X <- X + X (I - A X) in FP64.
 
-    The loop: R = I - A X; stop when ||R||_F is no longer below ``stall``
-    times the previous one (the FP64 rounding floor is reached), keeping the
-    iterate with the smaller residual; ``max_iters`` updates at most.  The
-    result is accepted when its relative residual ||R||_F / sqrt(n) is below
-    ``accept``; otherwise the caller falls back to the plain FP64 run.
-    Returns (X, updates, [||R_k||_F for every R computed], accepted).
+    The loop: R = I - A X.  An update is kept only if ||R||_F decreases;
+    once ||R||_F < 1 (where R_{k+1} = R_k^2 contracts quadratically), an
+    update that does not bring it below ``stall`` times the previous value
+    means the FP64 rounding floor is reached and the loop ends.  At most
+    ``max_iters`` updates.  The result is accepted when its final ||R||_F is
+    at most ``accept``; otherwise the caller falls back to the plain FP64 run.
+    Returns (X, updates kept, [||R_k||_F for every R computed], accepted).
     """
     A = np.asarray(A, dtype=np.float64)
     X = np.asarray(X0, dtype=np.float64).copy()
@@ -196,18 +197,20 @@ def newton_schulz(A, X0, max_iters: int = 10, stall: float = 0.5, accept: float 
     r = float(np.linalg.norm(R))
     norms = [r]
     updates = 0
-    while updates < max_iters and np.isfinite(r) and r > 0.0:
-        Xn = X + X @ R
-        Rn = eye - A @ Xn
-        rn = float(np.linalg.norm(Rn))
-        norms.append(rn)
-        if not np.isfinite(rn) or rn >= r:
-            break                      # no progress: keep the previous iterate
-        X, R, r = Xn, Rn, rn
-        updates += 1
-        if rn > stall * norms[-2]:
-            break                      # the rounding floor is reached
-    accepted = bool(np.isfinite(r) and r / np.sqrt(n) < accept)
+    if np.isfinite(r) and r > 0.0:
+        for it in range(1, max_iters + 1):
+            Xn = X + X @ R
+            Rn = eye - A @ Xn
+            rn = float(np.linalg.norm(Rn))
+            norms.append(rn)
+            if not rn < r:
+                break                      # no progress: keep the previous iterate
+            prev = r
+            X, R, r = Xn, Rn, rn
+            updates = it
+            if rn == 0.0 or (prev < 1.0 and rn > stall * prev):
+                break                      # the rounding floor is reached
+    accepted = bool(np.isfinite(r) and r <= accept)
     return X, updates, norms, accepted
 
 

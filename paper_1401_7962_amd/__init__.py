@@ -79,6 +79,9 @@ def load_library(path: str = LIB_PATH):
     lib.gj_workspace_size.restype = SZ
     lib.gj_status_string.argtypes = [I32]
     lib.gj_status_string.restype = ctypes.c_char_p
+    D = ctypes.c_double
+    lib.gj_dgemm.argtypes = [I32, I32, I32, D, P, I64, P, I64, D, P, I64, D, P, I64, P]
+    lib.gj_dgemm.restype = I32
     lib.gj_onchip_max_n.argtypes = [I32]
     lib.gj_onchip_max_n.restype = I32
     _lib = lib
@@ -86,7 +89,7 @@ def load_library(path: str = LIB_PATH):
 
 
 EXPORTS = ("gj_invert", "gj_invert_batched", "gj_det", "gj_workspace_size",
-           "gj_status_string", "gj_onchip_max_n")
+           "gj_status_string", "gj_onchip_max_n", "gj_dgemm")
 
 
 def make_opts(precision=GJ_PREC_FP64, want_resid=False, max_refine_iters=10, flags=0,
@@ -181,6 +184,25 @@ def gj_invert(A, X=None, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = 
                        ws.numel() * ws.element_size(), _stream_ptr(stream))
     _check(st)
     return X, ipiv, jpiv, res
+
+
+def gj_dgemm(A, B, C=None, D=None, alpha=1.0, beta=0.0, gamma=0.0, stream=None):
+    """D = alpha A B + beta C + gamma I on the FP64 matrix cores (2-D float64
+    CUDA tensors, unit column stride)."""
+    import torch
+    lib = load_library()
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise GJError("inner dimensions differ")
+    if D is None:
+        D = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    st = lib.gj_dgemm(M, N, K, float(alpha), _ptr(A), A.stride(0), _ptr(B), B.stride(0),
+                      float(beta), _ptr(C) if C is not None else None,
+                      C.stride(0) if C is not None else N, float(gamma), _ptr(D), D.stride(0),
+                      _stream_ptr(stream))
+    _check(st)
+    return D
 
 
 def gj_det(A, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = None, ws=None, stream=None):

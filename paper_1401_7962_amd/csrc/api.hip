@@ -232,12 +232,19 @@ bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
     return x < y + bn && y < x + an;
 }
 
+size_t resid_ws(int n);
+struct RefinedLayout;
+size_t refined_ws(int n);
+
 size_t single_ws(int n, const Opts &o, bool det_only) {
-    (void)det_only;
-    const bool fp32 = (o.precision == GJ_PREC_FP32_REFINED);
-    if (n <= kOnchipMax) return 256;
-    BigShape s = big_shape(n, fp32, big_threads(n, fp32));
-    return big_bufs(s, fp32, 0).end;
+    if (o.precision == GJ_PREC_FP32_REFINED) return refined_ws(n);
+    size_t need = 256;
+    if (n > kOnchipMax) {
+        BigShape s = big_shape(n, false, big_threads(n, false));
+        need = big_bufs(s, false, 0).end;
+    }
+    if (o.want_resid && !det_only) need = a256(need) + resid_ws(n);
+    return need;
 }
 
 gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx, int32_t *ipiv,
@@ -259,7 +266,7 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
             if (e != hipSuccess) return hip_fail(e);
         }
         hipError_t e = launch_onchip(fp32, nullptr, nullptr, 0, nullptr, md, 1, A, X, ipiv, jpiv,
-                                     res, o.zero_tol, eps_default, det_only ? 1 : 0, s);
+                                     res, o.zero_tol, eps_default, det_only ? 1 : 0, nullptr, s);
         if (e != hipSuccess) return hip_fail(e);
         if (o.events && o.events[1]) {
             e = hipEventRecord((hipEvent_t)o.events[1], s);
@@ -274,8 +281,226 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
     BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
     hipError_t e = launch_big(fp32, nt, nullptr, nullptr, d, nullptr, sh.nblk, sh.nblk, n,
                               det_only ? 0 : sh.nblk, o.zero_tol, eps_default, det_only ? 1 : 0,
-                              o.events, s);
+                              o.events, nullptr, s);
     if (e != hipSuccess) return hip_fail(e);
+    return GJ_OK;
+}
+
+
+// ------------------------------------------------------------ refined path
+constexpr int kDetBlock = 128;          // diagonal blocks of the FP64 determinant
+constexpr double kAcceptResid = 1e-2;   // ||I - A X||_F above this: fall back to FP64
+constexpr double kStall = 0.5;          // an update must at least halve ||R||_F
+
+struct RefinedLayout {
+    size_t ctl, big32, xw, r, over64, t, dinv, part_r, part_a, part_x, blockres, rows, cols, bpiv, end;
+    int nparts;
+};
+
+RefinedLayout refined_layout(int n) {
+    RefinedLayout L;
+    size_t c = 0;
+    const size_t n2 = (size_t)n * n * 8;
+    L.ctl = c; c = a256(c + refine_ctl_bytes());
+    L.big32 = c;
+    if (n > kOnchipMax) {
+        BigShape s = big_shape(n, true, big_threads(n, true));
+        c = big_bufs(s, true, c).end;
+    }
+    // the FP64 fallback's buffers overlay the second iterate and R: it runs
+    // only when neither is needed any more
+    L.xw = c;
+    L.over64 = c;
+    size_t over = 2 * n2;
+    if (n > kOnchipMax) {
+        BigShape s = big_shape(n, false, big_threads(n, false));
+        over = std::max(over, big_bufs(s, false, 0).end);
+    }
+    L.r = a256(c + n2);
+    c = a256(c + std::max(over, a256(n2) + n2));
+    L.t = c; c = a256(c + (size_t)kDetBlock * n * 8);
+    L.dinv = c; c = a256(c + (size_t)kDetBlock * kDetBlock * 8);
+    L.nparts = std::max(gemm_tiles(n, n), sumsq_blocks(n));
+    L.part_r = c; c = a256(c + (size_t)L.nparts * 8);
+    L.part_a = c; c = a256(c + (size_t)L.nparts * 8);
+    L.part_x = c; c = a256(c + (size_t)L.nparts * 8);
+    L.blockres = c; c = a256(c + (size_t)((n + kDetBlock - 1) / kDetBlock) * sizeof(gj_result));
+    L.rows = c; c = a256(c + (size_t)n * 4);
+    L.cols = c; c = a256(c + (size_t)n * 4);
+    L.bpiv = c; c = a256(c + 2 * kDetBlock * 4);
+    L.end = c;
+    return L;
+}
+
+#define GJ_TRY(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) return hip_fail(e_); } while (0)
+
+// Eliminate in FP32 (the pivots and X0), refine X in FP64, FP64 determinant.
+gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int64_t ldx,
+                             int32_t *ipiv, int32_t *jpiv, gj_result *res, const Opts &o, char *w,
+                             hipStream_t s, bool det_only) {
+    const RefinedLayout L = refined_layout(n);
+    void *ctl = w + L.ctl;
+    double *Xw = reinterpret_cast<double *>(w + L.xw);
+    double *R = reinterpret_cast<double *>(w + L.r);
+    double *T = reinterpret_cast<double *>(w + L.t);
+    double *Dinv = reinterpret_cast<double *>(w + L.dinv);
+    double *pr = reinterpret_cast<double *>(w + L.part_r);
+    double *pa = reinterpret_cast<double *>(w + L.part_a);
+    double *px = reinterpret_cast<double *>(w + L.part_x);
+    gj_result *blockres = reinterpret_cast<gj_result *>(w + L.blockres);
+    int32_t *rows = reinterpret_cast<int32_t *>(w + L.rows);
+    int32_t *cols = reinterpret_cast<int32_t *>(w + L.cols);
+    int32_t *bpiv = reinterpret_cast<int32_t *>(w + L.bpiv);
+    const int det = det_only ? 1 : 1;  // the refined path always returns the FP64 determinant
+
+    // 1. FP32 elimination (zero threshold 0): X0 in X, pivots, FP32 status
+    BigDesc d32;
+    std::memset(&d32, 0, sizeof(d32));
+    if (n <= kOnchipMax) {
+        MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0};
+        if (o.events && o.events[0]) GJ_TRY(hipEventRecord((hipEvent_t)o.events[0], s));
+        GJ_TRY(launch_onchip(true, nullptr, nullptr, 0, nullptr, md, 1, A, det_only ? nullptr : X,
+                             ipiv, jpiv, res, 0.0, 0.0, det_only ? 1 : 0, nullptr, s));
+        if (o.events && o.events[1]) GJ_TRY(hipEventRecord((hipEvent_t)o.events[1], s));
+    } else {
+        const int nt = big_threads(n, true);
+        BigShape sh = big_shape(n, true, nt);
+        BigBufs bb = big_bufs(sh, true, L.big32);
+        d32 = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
+        GJ_TRY(launch_big(true, nt, nullptr, nullptr, d32, nullptr, sh.nblk, sh.nblk, n,
+                          det_only ? 0 : sh.nblk, 0.0, 0.0, det_only ? 1 : 0, o.events, nullptr, s));
+    }
+    GJ_TRY(launch_refine_start(res, ctl, s));
+
+    // 2. Newton-Schulz: R = I - A X; X' = X + X R; keep while ||R||_F drops
+    const int nparts = gemm_tiles(n, n);
+    if (!det_only) {
+        GemmArgs g;
+        std::memset(&g, 0, sizeof(g));
+        g.M = g.N = g.K = n;
+        g.A = A; g.lda = lda; g.B = X; g.ldb = ldx; g.D = R; g.ldd = n;
+        g.alpha = -1.0; g.beta = 0.0; g.gamma = 1.0;
+        g.norm_partials = pr; g.run_flag = ctl_run_ns(ctl);
+        GJ_TRY(launch_gemm_f64(g, s));
+        GJ_TRY(launch_refine_resid0(pr, nparts, ctl, s));
+        for (int it = 1; it <= o.max_refine_iters; ++it) {
+            double *Xs = ((it - 1) & 1) ? Xw : X;
+            double *Xd = (it & 1) ? Xw : X;
+            const int64_t lds = ((it - 1) & 1) ? n : ldx, ldd = (it & 1) ? n : ldx;
+            GemmArgs u;
+            std::memset(&u, 0, sizeof(u));
+            u.M = u.N = u.K = n;
+            u.A = Xs; u.lda = lds; u.B = R; u.ldb = n; u.C = Xs; u.ldc = lds; u.D = Xd; u.ldd = ldd;
+            u.alpha = 1.0; u.beta = 1.0; u.gamma = 0.0;
+            u.run_flag = ctl_run_ns(ctl);
+            GJ_TRY(launch_gemm_f64(u, s));
+            GemmArgs r2 = g;
+            r2.B = Xd; r2.ldb = ldd;
+            GJ_TRY(launch_gemm_f64(r2, s));
+            GJ_TRY(launch_refine_after_update(pr, nparts, ctl, it, o.max_refine_iters, kStall, s));
+        }
+        GJ_TRY(launch_refine_finish(ctl, kAcceptResid, det, s));
+        GJ_TRY(launch_copy_flagged(Xw, n, X, ldx, n, ctl_copy_back(ctl), s));
+    } else {
+        GJ_TRY(launch_refine_finish(ctl, __builtin_inf(), det, s));
+    }
+
+    // 3. fallback: the plain FP64 elimination, only when flagged
+    if (n <= kOnchipMax) {
+        MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0};
+        GJ_TRY(launch_onchip(false, nullptr, nullptr, 0, nullptr, md, 1, A, det_only ? nullptr : X,
+                             ipiv, jpiv, res, o.zero_tol, kEps64, det_only ? 1 : 0,
+                             ctl_run_fallback(ctl), s));
+    } else {
+        const int nt = big_threads(n, false);
+        BigShape sh = big_shape(n, false, nt);
+        BigBufs bb = big_bufs(sh, false, L.over64);
+        BigDesc d = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
+        GJ_TRY(launch_big(false, nt, nullptr, nullptr, d, nullptr, sh.nblk, sh.nblk, n,
+                          det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
+                          ctl_run_fallback(ctl), s));
+    }
+    GJ_TRY(launch_fallback_mark(res, ctl, s));
+
+    // 4. FP64 determinant: permute A with the FP32 order, block elimination
+    const int32_t *fdet = ctl_run_det(ctl);
+    const int32_t *prow = rows, *pcol = cols;
+    if (n <= kOnchipMax) {
+        GJ_TRY(launch_perms_from_pivots(ipiv, jpiv, n, rows, cols, fdet, s));
+    } else {
+        prow = d32.rowphys;
+        pcol = d32.colphys;
+    }
+    double *B = R;
+    GJ_TRY(launch_gather_perm(A, lda, prow, pcol, n, B, n, fdet, s));
+    const int nblocks = (n + kDetBlock - 1) / kDetBlock;
+    for (int kb = 0, bi = 0; kb < n; kb += kDetBlock, ++bi) {
+        const int nbk = std::min(kDetBlock, n - kb);
+        MatDesc md{(int64_t)kb * n + kb, 0, 0, nbk, n, kDetBlock, 0};
+        GJ_TRY(launch_onchip(false, nullptr, nullptr, 0, nullptr, md, 1, B, Dinv, bpiv,
+                             bpiv + kDetBlock, blockres + bi, -1.0, kEps64, 0, fdet, s));
+        const int m = n - kb - nbk;
+        if (m > 0) {
+            GemmArgs g1;
+            std::memset(&g1, 0, sizeof(g1));
+            g1.M = nbk; g1.N = m; g1.K = nbk;
+            g1.A = Dinv; g1.lda = kDetBlock;
+            g1.B = B + (int64_t)kb * n + kb + nbk; g1.ldb = n;
+            g1.D = T; g1.ldd = n;
+            g1.alpha = 1.0; g1.run_flag = fdet;
+            GJ_TRY(launch_gemm_f64(g1, s));
+            GemmArgs g2;
+            std::memset(&g2, 0, sizeof(g2));
+            g2.M = m; g2.N = m; g2.K = nbk;
+            g2.A = B + (int64_t)(kb + nbk) * n + kb; g2.lda = n;
+            g2.B = T; g2.ldb = n;
+            g2.C = B + (int64_t)(kb + nbk) * n + kb + nbk; g2.ldc = n;
+            g2.D = const_cast<double *>(g2.C); g2.ldd = n;
+            g2.alpha = -1.0; g2.beta = 1.0; g2.run_flag = fdet;
+            GJ_TRY(launch_gemm_f64(g2, s));
+        }
+    }
+    GJ_TRY(launch_det_combine(blockres, nblocks, ipiv, jpiv, n, res, ctl, s));
+    GJ_TRY(launch_refine_iters(res, ctl, s));
+
+    // 5. optional residual of the returned inverse
+    if (o.want_resid && !det_only) {
+        GemmArgs g;
+        std::memset(&g, 0, sizeof(g));
+        g.M = g.N = g.K = n;
+        g.A = A; g.lda = lda; g.B = X; g.ldb = ldx; g.D = R; g.ldd = n;
+        g.alpha = -1.0; g.gamma = 1.0; g.norm_partials = pr;
+        GJ_TRY(launch_gemm_f64(g, s));
+        GJ_TRY(launch_sumsq(A, lda, n, pa, s));
+        GJ_TRY(launch_sumsq(X, ldx, n, px, s));
+        GJ_TRY(launch_resid(pr, nparts, pa, sumsq_blocks(n), px, sumsq_blocks(n), res, s));
+    }
+    return GJ_OK;
+}
+
+size_t refined_ws(int n) { return refined_layout(n).end; }
+
+// Residual of a plain FP64 result (want_resid): needs n^2 + partial sums.
+size_t resid_ws(int n) {
+    return a256((size_t)n * n * 8) + 3 * a256((size_t)std::max(gemm_tiles(n, n), sumsq_blocks(n)) * 8);
+}
+
+gj_status run_resid(int n, const double *A, int64_t lda, const double *X, int64_t ldx,
+                    gj_result *res, char *w, hipStream_t s) {
+    double *R = reinterpret_cast<double *>(w);
+    const size_t np = a256((size_t)std::max(gemm_tiles(n, n), sumsq_blocks(n)) * 8);
+    double *pr = reinterpret_cast<double *>(w + a256((size_t)n * n * 8));
+    double *pa = reinterpret_cast<double *>((char *)pr + np);
+    double *px = reinterpret_cast<double *>((char *)pa + np);
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.M = g.N = g.K = n;
+    g.A = A; g.lda = lda; g.B = X; g.ldb = ldx; g.D = R; g.ldd = n;
+    g.alpha = -1.0; g.gamma = 1.0; g.norm_partials = pr;
+    GJ_TRY(launch_gemm_f64(g, s));
+    GJ_TRY(launch_sumsq(A, lda, n, pa, s));
+    GJ_TRY(launch_sumsq(X, ldx, n, px, s));
+    GJ_TRY(launch_resid(pr, gemm_tiles(n, n), pa, sumsq_blocks(n), px, sumsq_blocks(n), res, s));
     return GJ_OK;
 }
 
@@ -301,6 +526,26 @@ const char *gj_status_string(int32_t code) {
     return "unknown code";
 }
 
+gj_status gj_dgemm(int32_t M, int32_t N, int32_t K, double alpha, const double *A, int64_t lda,
+                   const double *B, int64_t ldb, double beta, const double *C, int64_t ldc,
+                   double gamma, double *D, int64_t ldd, void *stream) {
+    try {
+        if (M < 0 || N < 0 || K < 0 || !D || ldd < N) return GJ_E_INVALID_ARG;
+        if (K > 0 && (!A || !B || lda < K || ldb < N)) return GJ_E_INVALID_ARG;
+        if (beta != 0.0 && (!C || ldc < N)) return GJ_E_INVALID_ARG;
+        GemmArgs g;
+        std::memset(&g, 0, sizeof(g));
+        g.M = M; g.N = N; g.K = K;
+        g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+        g.alpha = alpha; g.beta = beta; g.gamma = gamma;
+        hipError_t e = launch_gemm_f64(g, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e);
+        return GJ_OK;
+    } catch (...) {
+        return GJ_E_HIP;
+    }
+}
+
 int32_t gj_onchip_max_n(int32_t precision) {
     (void)precision;
     return kOnchipMax;
@@ -323,6 +568,10 @@ size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
     return 0;
 }
 
+static bool needs_ws(int n, const Opts &o, bool det_only) {
+    return n > kOnchipMax || o.precision == GJ_PREC_FP32_REFINED || (o.want_resid && !det_only);
+}
+
 gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t ldx,
                     int32_t *ipiv, int32_t *jpiv, gj_result *res, const gj_opts *opts, void *ws,
                     size_t ws_bytes, void *stream) {
@@ -332,18 +581,23 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
         if (n < 1 || lda < n || ldx < n || !A || !X || !ipiv || !jpiv || !res)
             return GJ_E_INVALID_ARG;
         if (n > kMaxN) return GJ_E_UNSUPPORTED;
-        if (o.precision != GJ_PREC_FP64) return GJ_E_UNSUPPORTED;
         const size_t abytes = ((size_t)(n - 1) * lda + n) * 8, xbytes = ((size_t)(n - 1) * ldx + n) * 8;
         if (overlaps(A, abytes, X, xbytes)) return GJ_E_INVALID_ARG;
         const size_t need = single_ws(n, o, false);
-        if (n > kOnchipMax) {
+        if (needs_ws(n, o, false)) {
             if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
             if (ws_bytes < need) return GJ_E_WORKSPACE;
             if (overlaps(ws, ws_bytes, X, xbytes) || overlaps(ws, ws_bytes, A, abytes))
                 return GJ_E_INVALID_ARG;
         }
-        return run_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes,
-                          (hipStream_t)stream, false);
+        hipStream_t s = (hipStream_t)stream;
+        if (o.precision == GJ_PREC_FP32_REFINED)
+            return run_refined_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, (char *)ws, s, false);
+        gj_status st = run_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes, s, false);
+        if (st != GJ_OK || !o.want_resid) return st;
+        size_t off = 0;
+        if (n > kOnchipMax) off = a256(big_bufs(big_shape(n, false, big_threads(n, false)), false, 0).end);
+        return run_resid(n, A, lda, X, ldx, res, (char *)ws + off, s);
     } catch (...) {
         return GJ_E_HIP;
     }
@@ -356,14 +610,15 @@ gj_status gj_det(int32_t n, const double *A, int64_t lda, int32_t *ipiv, int32_t
         if (!read_opts(opts, o)) return GJ_E_INVALID_ARG;
         if (n < 1 || lda < n || !A || !ipiv || !jpiv || !res) return GJ_E_INVALID_ARG;
         if (n > kMaxN) return GJ_E_UNSUPPORTED;
-        if (o.precision != GJ_PREC_FP64) return GJ_E_UNSUPPORTED;
         const size_t need = single_ws(n, o, true);
-        if (n > kOnchipMax) {
+        if (needs_ws(n, o, true)) {
             if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
             if (ws_bytes < need) return GJ_E_WORKSPACE;
         }
-        return run_single(n, A, lda, nullptr, n, ipiv, jpiv, res, o, ws, ws_bytes,
-                          (hipStream_t)stream, true);
+        hipStream_t s = (hipStream_t)stream;
+        if (o.precision == GJ_PREC_FP32_REFINED)
+            return run_refined_single(n, A, lda, nullptr, n, ipiv, jpiv, res, o, (char *)ws, s, true);
+        return run_single(n, A, lda, nullptr, n, ipiv, jpiv, res, o, ws, ws_bytes, s, true);
     } catch (...) {
         return GJ_E_HIP;
     }
@@ -439,7 +694,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
                                          reinterpret_cast<const OnchipTask *>(w + P.off_tasks),
                                          (int)P.tasks.size(),
                                          reinterpret_cast<uint32_t *>(w + P.off_queue), MatDesc(),
-                                         grid, A, X, ipiv, jpiv, res, o.zero_tol, eps_default, 0, s);
+                                         grid, A, X, ipiv, jpiv, res, o.zero_tol, eps_default, 0, nullptr, s);
             if (e != hipSuccess) return hip_fail(e);
         }
         if (!P.big_members.empty()) {
@@ -447,7 +702,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
             hipError_t e = launch_big(fp32, P.big_nt, reinterpret_cast<const BigDesc *>(w + P.off_descs),
                                       reinterpret_cast<const int2 *>(w + P.off_bmap), BigDesc(),
                                       P.grid_per_step.data(), nb, nb, P.big_max_n, nb, o.zero_tol,
-                                      eps_default, 0, o.events, s);
+                                      eps_default, 0, o.events, nullptr, s);
             if (e != hipSuccess) return hip_fail(e);
         }
         return GJ_OK;

@@ -73,7 +73,9 @@ __device__ inline void block_argmax(double &a, double &v, uint32_t &key, int &ip
 // W <- A (converted to T), identity maps, pivot candidates of step 0.
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
-gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single) {
+gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
+              const int32_t *__restrict__ run_flag) {
+    if (run_flag && *run_flag == 0) return;
     __shared__ double s_a[NT / kWave], s_v[NT / kWave];
     __shared__ uint32_t s_k[NT / kWave];
     __shared__ int s_i[NT / kWave], s_j[NT / kWave];
@@ -123,7 +125,9 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT)
 gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
-            int k, double zero_tol, double eps_default, int det_only) {
+            int k, double zero_tol, double eps_default, int det_only,
+            const int32_t *__restrict__ run_flag) {
+    if (run_flag && *run_flag == 0) return;
     using V = VecOf<T>;
     using VT = typename V::type;
     using VI = typename V::itype;
@@ -299,7 +303,9 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 // Inverse maps, pivot sequence, determinant and result record.
 template <typename T>
 __global__ void __launch_bounds__(256)
-gj_big_finish(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single) {
+gj_big_finish(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
+              const int32_t *__restrict__ run_flag) {
+    if (run_flag && *run_flag == 0) return;
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
     const int n = d.n, t = threadIdx.x;
@@ -344,7 +350,9 @@ gj_big_finish(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
 // still needs its eq. 14 division.  One workgroup per output row.
 template <typename T>
 __global__ void __launch_bounds__(256)
-gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single) {
+gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
+              const int32_t *__restrict__ run_flag) {
+    if (run_flag && *run_flag == 0) return;
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
     const int n = d.n, t = threadIdx.x;
@@ -380,8 +388,8 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
                             const int *grid_per_step,
                             int grid_init, int grid_finish, int max_n, int gather_grid,
                             double zero_tol, double eps_default, int det_only, void *const *events,
-                            hipStream_t s) {
-    hipLaunchKernelGGL((gj_big_init<T, NT>), dim3(grid_init), dim3(NT), 0, s, descs, bmap, single);
+                            const int32_t *run_flag, hipStream_t s) {
+    hipLaunchKernelGGL((gj_big_init<T, NT>), dim3(grid_init), dim3(NT), 0, s, descs, bmap, single, run_flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (events && events[0]) {
@@ -390,7 +398,8 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
     }
     for (int k = 0; k < max_n; ++k) {
         hipLaunchKernelGGL((gj_big_step<T, NT>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
-                           dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only);
+                           dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only,
+                           run_flag);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -398,11 +407,11 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         e = hipEventRecord((hipEvent_t)events[1], s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((gj_big_finish<T>), dim3(grid_finish), dim3(256), 0, s, descs, bmap, single);
+    hipLaunchKernelGGL((gj_big_finish<T>), dim3(grid_finish), dim3(256), 0, s, descs, bmap, single, run_flag);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (!det_only && gather_grid > 0) {
-        hipLaunchKernelGGL((gj_big_gather<T>), dim3(gather_grid), dim3(256), 0, s, descs, bmap, single);
+        hipLaunchKernelGGL((gj_big_gather<T>), dim3(gather_grid), dim3(256), 0, s, descs, bmap, single, run_flag);
         e = hipGetLastError();
     }
     return e;
@@ -411,10 +420,10 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
 hipError_t launch_big(bool fp32, int nt, const BigDesc *descs, const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
-                      void *const *events, hipStream_t s) {
+                      void *const *events, const int32_t *run_flag, hipStream_t s) {
 #define GJ_BIG_CASE(TT, NTV)                                                                \
     return run_big_t<TT, NTV>(descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n,   \
-                              gather_grid, zero_tol, eps_default, det_only, events, s)
+                              gather_grid, zero_tol, eps_default, det_only, events, run_flag, s)
     if (fp32) {
         switch (nt) {
             case 256: GJ_BIG_CASE(float, 256);

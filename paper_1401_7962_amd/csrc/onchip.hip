@@ -386,10 +386,11 @@ gj_onchip_kernel(const MatDesc *__restrict__ mats, const OnchipTask *__restrict_
                  int ntasks, uint32_t *__restrict__ queue, const MatDesc single,
                  const double *__restrict__ A, double *__restrict__ X, int32_t *__restrict__ ipiv,
                  int32_t *__restrict__ jpiv, gj_result *__restrict__ res, double zero_tol,
-                 double eps_default, int det_only) {
+                 double eps_default, int det_only, const int32_t *__restrict__ run_flag) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[OnchipShared<T>::bytes];
     __shared__ int s_task;
     const int t = threadIdx.x;
+    if (run_flag && *run_flag == 0) return;
     if (mats == nullptr) {
         if (blockIdx.x == 0)
             run_kind0<T>(smem, t, single, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only);
@@ -433,7 +434,8 @@ hipError_t launch_zero_u32(uint32_t *p, int count, hipStream_t s) {
 hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks, int ntasks,
                          uint32_t *queue, const MatDesc &single, int grid, const double *A,
                          double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res, double zero_tol,
-                         double eps_default, int det_only, hipStream_t s) {
+                         double eps_default, int det_only, const int32_t *run_flag,
+                         hipStream_t s) {
     if (mats) {
         hipError_t e = launch_zero_u32(queue, 1, s);
         if (e != hipSuccess) return e;
@@ -441,11 +443,11 @@ hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks
     if (fp32)
         hipLaunchKernelGGL(gj_onchip_kernel<float>, dim3(grid), dim3(256), 0, s, mats, tasks,
                            ntasks, queue, single, A, X, ipiv, jpiv, res, zero_tol, eps_default,
-                           det_only);
+                           det_only, run_flag);
     else
         hipLaunchKernelGGL(gj_onchip_kernel<double>, dim3(grid), dim3(256), 0, s, mats, tasks,
                            ntasks, queue, single, A, X, ipiv, jpiv, res, zero_tol, eps_default,
-                           det_only);
+                           det_only, run_flag);
     return hipGetLastError();
 }
 

@@ -1,0 +1,120 @@
+"""GPU parity for the FP32-elimination + FP64-refinement path.
+
+Bars (tolerances derived in the design doc):
+* the FP32 elimination is the oracle's FP32 model operation for operation, so
+  the returned pivot sequence equals the FP32 oracle's bit for bit;
+* for cond <= 1e4 the refined inverse is within 1e-12 (relative Frobenius) of
+  the FP64 oracle's inverse;
+* for every condition number its forward error against the long-double
+  oracle is at most 4x the FP64 oracle's own error plus 1e-14;
+* the Newton-Schulz update count is within one of the oracle's loop run from
+  the same FP32 starting inverse;
+* the FP64 determinant agrees with the static-pivot LU oracle (same pivot
+  order) and with the closed form n ln(cond) / 2 of the test matrices.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1401_7962_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gj():
+    import torch  # noqa: F401
+    import paper_1401_7962_amd as m
+    m.load_library()
+    return m
+
+
+def _refined(gj, A, det_only=False, **kw):
+    import torch
+    opts = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, **kw)
+    Ad = torch.from_numpy(np.ascontiguousarray(A)).to("cuda")
+    if det_only:
+        ipiv, jpiv, res = gj.gj_det(Ad, opts=opts)
+        torch.cuda.synchronize()
+        return None, ipiv.cpu().numpy(), jpiv.cpu().numpy(), gj.results_to_dicts(res)[0]
+    X, ipiv, jpiv, res = gj.gj_invert(Ad, opts=opts)
+    torch.cuda.synchronize()
+    return X.cpu().numpy(), ipiv.cpu().numpy(), jpiv.cpu().numpy(), gj.results_to_dicts(res)[0]
+
+
+def _rel(Y, Z):
+    return float(np.linalg.norm(Y - Z) / np.linalg.norm(Z))
+
+
+CASES = [(n, c) for n in (48, 128, 200, 333) for c in (1e2, 1e4, 1e6, 1e8)]
+
+
+@pytest.mark.parametrize("n,cond", CASES)
+def test_refined_inverse(gj, n, cond):
+    A = inputs.conditioned(n, cond, inputs.rng_for(0, 6000 + n))
+    X, ipiv, jpiv, r = _refined(gj, A)
+    assert r["code"] == 0, r
+    # FP32 stage: pivot sequence identical to the FP32 oracle
+    X32, i32, j32, _ = oracle.gj_invert_f32(A.astype(np.float32))
+    assert np.array_equal(ipiv, i32) and np.array_equal(jpiv, j32)
+    Xo, _, _, ro = oracle.gj_invert_f64(A)
+    Xt, _, _, _ = oracle.gj_invert_f80(A)
+    if cond <= 1e4:
+        assert _rel(X, Xo) <= 1e-12
+    assert _rel(X, Xt) <= 4 * _rel(Xo, Xt) + 1e-14
+    # Newton-Schulz: same number of kept updates (within one) as the oracle loop
+    _, upd, norms, acc = oracle.newton_schulz(A, X32.astype(np.float64))
+    assert abs(r["refine_iters"] - upd) <= 1, (r["refine_iters"], upd, norms)
+    # FP64 determinant
+    lu = oracle.lu_static_det_f64(A, i32, j32)
+    assert r["det_sign"] == lu["det_sign"] == 1
+    assert abs(r["logabsdet"] - lu["logabsdet"]) <= max(1e-12, n * cond * 2.0 ** -53) * abs(lu["logabsdet"])
+    if cond <= 1e6:
+        cf = inputs.closed_form_logdet(n, cond)
+        assert abs(r["logabsdet"] - cf) <= 1e-9 * abs(cf)
+
+
+@pytest.mark.parametrize("n", [64, 300])
+def test_refined_det_only(gj, n):
+    A = inputs.conditioned(n, 1e3, inputs.rng_for(0, 6100 + n))
+    _, ipiv, jpiv, r = _refined(gj, A, det_only=True)
+    _, i32, j32, _ = oracle.gj_invert_f32(A.astype(np.float32))
+    assert np.array_equal(ipiv, i32) and np.array_equal(jpiv, j32)
+    lu = oracle.lu_static_det_f64(A, i32, j32)
+    assert r["det_sign"] == lu["det_sign"]
+    assert abs(r["logabsdet"] - lu["logabsdet"]) <= 1e-12 * abs(lu["logabsdet"])
+
+
+@pytest.mark.parametrize("n", [40, 260])
+def test_fallback_when_fp32_underflows(gj, n):
+    """Entries below the FP32 range: the FP32 elimination sees a zero matrix
+    (singular), so the FP64 elimination produces the result, bit for bit."""
+    A = inputs.rng_for(0, 6200 + n).standard_normal((n, n)) * 1e-50
+    X, ipiv, jpiv, r = _refined(gj, A)
+    Xo, io, jo, ro = oracle.gj_invert_f64(A)
+    assert r["code"] == 3
+    assert X.tobytes() == Xo.tobytes()
+    assert np.array_equal(ipiv, io) and np.array_equal(jpiv, jo)
+    assert r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"]
+
+
+@pytest.mark.parametrize("n", [64, 256])
+def test_singular_through_refined_path(gj, n):
+    H = inputs.sylvester_hadamard(n)
+    A = H.copy()
+    A[:, n - 1] = H[:, 0] + H[:, 1]
+    X, ipiv, jpiv, r = _refined(gj, A)
+    assert r["code"] == 1 and r["rank"] == n - 1
+    assert np.isnan(X).all()
+
+
+@pytest.mark.parametrize("n,prec", [(70, 0), (300, 0), (70, 1), (300, 1)])
+def test_want_resid(gj, n, prec):
+    import torch
+    A = inputs.conditioned(n, 1e3, inputs.rng_for(0, 6300 + n))
+    opts = gj.make_opts(precision=prec, want_resid=True)
+    X, _, _, res = gj.gj_invert(torch.from_numpy(A).to("cuda"), opts=opts)
+    torch.cuda.synchronize()
+    r = gj.results_to_dicts(res)[0]
+    want = oracle.residual(A, X.cpu().numpy())
+    assert abs(r["resid"] - want) <= 1e-2 * want + 1e-18
