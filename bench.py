@@ -114,6 +114,139 @@ def bench_headline(steps: int, warmup: int, n: int = 4096):
     }
 
 
+def _events(n, stream):
+    import torch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+    for e in ev:
+        e.record(stream)
+    return ev
+
+
+def bench_latency_small(reps: int = 200):
+    """64 x 64 N(0,1) and the 3 x 3 Pascal matrix: microseconds per inversion,
+    one inversion per replay of a captured HIP graph."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    out = {}
+    for name, A_h in (("normal64", inputs.single_normal(64)), ("pascal3", inputs.pascal(3))):
+        n = A_h.shape[0]
+        A = torch.from_numpy(A_h).cuda()
+        X = torch.empty_like(A)
+        ip = torch.empty(n, dtype=torch.int32, device="cuda")
+        jp = torch.empty_like(ip)
+        res = torch.empty(gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(256, dtype=torch.uint8, device="cuda")
+        gj.gj_invert(A, X, ip, jp, res, None, ws)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                gj.gj_invert(A, X, ip, jp, res, None, ws, s)
+        torch.cuda.synchronize()
+        e0, e1 = _events(2, torch.cuda.current_stream())
+        e0.record()
+        for _ in range(reps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        r = gj.results_to_dicts(res)[0]
+        out[name] = {"n": n, "us_per_inversion": round(us, 2), "code": r["code"], "det": r["det"]}
+    return out
+
+
+def bench_batch_uneven(batch: int = 100_000, reps: int = 3):
+    """100,000 FP64 matrices, n uniform in [8,128], 1% rank n-1: one persistent
+    on-chip launch.  Reports inversions/s and FP64 FMA throughput (n^3 FMAs =
+    2 n^3 flop per inversion)."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    sizes, offs, packed, singular = inputs.batch_uneven(batch)
+    A = torch.from_numpy(packed).cuda()
+    del packed
+    X = torch.empty_like(A)
+    poff = np.zeros(batch, dtype=np.int64)
+    poff[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
+    ip = torch.empty(int(sizes.sum()), dtype=torch.int32, device="cuda")
+    jp = torch.empty_like(ip)
+    res = torch.empty(batch * gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, batch, sizes), dtype=torch.uint8,
+                     device="cuda")
+    gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, None, ws)   # uploads the plan
+    torch.cuda.synchronize()
+    reuse = gj.make_opts(flags=gj.GJ_FLAG_REUSE_PLAN)
+    stream = torch.cuda.current_stream()
+    e = _events(2 * reps, stream)
+    for k in range(reps):
+        e[2 * k].record()
+        gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, reuse, ws)
+        e[2 * k + 1].record()
+    torch.cuda.synchronize()
+    ms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+    codes = np.frombuffer(res.cpu().numpy().tobytes(), dtype=np.int32).reshape(batch, 14)[:, 0]
+    flops = 2.0 * float((sizes.astype(np.float64) ** 3).sum())
+    return {
+        "batch": batch,
+        "ms": round(ms, 3),
+        "inversions_per_s": round(batch / (ms * 1e-3), 1),
+        "fp64_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+        "frac_of_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "singular_flagged": int((codes == 1).sum()),
+        "singular_planted": int(len(singular)),
+        "other_codes": int(((codes != 0) & (codes != 1)).sum()),
+    }
+
+
+def bench_conditioned_8192(n: int = 8192, reps: int = 2):
+    """U diag(s) V^T, s log-spaced 1..1e6: plain FP64 elimination against FP32
+    elimination + FP64 Newton-Schulz refinement, with the residual of each
+    result and the refined result's distance from the plain FP64 result."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    t0 = time.perf_counter()
+    A = inputs.single_conditioned(n, device="cuda")   # Gaussian draws on the host, QR on the GPU
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    out = {"n": n, "cond": 1e6, "input_generation_s": round(gen_s, 1),
+           "closed_form_logabsdet": inputs.closed_form_logdet(n, 1e6)}
+    Xs = {}
+    stream = torch.cuda.current_stream()
+    for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
+        opts = gj.make_opts(precision=prec)
+        X = torch.empty_like(A)
+        ip = torch.empty(n, dtype=torch.int32, device="cuda")
+        jp = torch.empty_like(ip)
+        res = torch.empty(gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(gj.gj_workspace_size(gj.GJ_OP_INVERT, n, None, opts), dtype=torch.uint8,
+                         device="cuda")
+        gj.gj_invert(A, X, ip, jp, res, opts, ws)
+        torch.cuda.synchronize()
+        e = _events(2 * reps, stream)
+        for k in range(reps):
+            e[2 * k].record()
+            gj.gj_invert(A, X, ip, jp, res, opts, ws)
+            e[2 * k + 1].record()
+        torch.cuda.synchronize()
+        ms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+        r = gj.results_to_dicts(res)[0]
+        del ws
+        R = gj.gj_dgemm(A, X, gamma=1.0, alpha=-1.0)
+        resid = float(torch.linalg.norm(R) / (torch.linalg.norm(A) * torch.linalg.norm(X)))
+        del R
+        out[name] = {"ms": round(ms, 1), "inversions_per_s": round(1e3 / ms, 4), "code": r["code"],
+                     "refine_iters": r["refine_iters"], "logabsdet": r["logabsdet"],
+                     "det_sign": r["det_sign"], "resid": resid}
+        Xs[name] = X
+    d = float(torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"]))
+    out["refined_vs_plain_rel_frobenius"] = d
+    out["speedup_refined_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined"]["ms"], 3)
+    return out
+
+
 def ctypes_ptr(event):
     """hipEvent_t handle of a torch.cuda.Event."""
     return event.cuda_event
@@ -148,6 +281,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the secondary workloads (latency, batch, refined 8192)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy, whose rocprofv3 FETCH_SIZE and "
                          "WRITE_SIZE calibrate the counters")
@@ -204,6 +339,17 @@ def main():
         "checks": {"resid": head["resid"], "logabsdet": head["logabsdet"],
                    "det_sign": head["det_sign"]},
     }
+    if not args.headline_only:
+        extras = {}
+        extras["latency_small"] = bench_latency_small()
+        print("bench: small-matrix latency done", file=sys.stderr, flush=True)
+        extras["batch_uneven_100k"] = bench_batch_uneven()
+        print("bench: 100k batch done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["conditioned_8192"] = bench_conditioned_8192()
+        print("bench: 8192 plain vs refined done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(out), flush=True)

@@ -81,11 +81,24 @@ def batch_uneven(batch: int = 100_000, nmin: int = 8, nmax: int = 128,
     return sizes, offs, packed, singular
 
 
-def haar_orthogonal(n: int, rng: np.random.Generator) -> np.ndarray:
+def haar_orthogonal(n: int, rng: np.random.Generator, device=None):
     """Haar-distributed orthogonal matrix with determinant +1: QR of a
     Gaussian matrix with the signs of diag(R) moved into Q, then column 0
-    negated if the determinant is -1."""
+    negated if the determinant is -1.  With ``device`` (a torch device) the
+    same Gaussian draws are factored there (for large n) and a torch tensor
+    is returned."""
     Z = rng.standard_normal((n, n))
+    if device is not None:
+        import torch
+        Zt = torch.from_numpy(Z).to(device)
+        del Z
+        Q, R = torch.linalg.qr(Zt)
+        del Zt
+        Q *= torch.sign(torch.diagonal(R))[None, :]
+        del R
+        if torch.linalg.slogdet(Q)[0].item() < 0:
+            Q[:, 0] = -Q[:, 0]
+        return Q
     Q, R = np.linalg.qr(Z)
     Q *= np.sign(np.diag(R))[None, :]
     if np.linalg.slogdet(Q)[0] < 0:
@@ -93,17 +106,22 @@ def haar_orthogonal(n: int, rng: np.random.Generator) -> np.ndarray:
     return Q
 
 
-def conditioned(n: int, cond: float, rng: np.random.Generator) -> np.ndarray:
+def conditioned(n: int, cond: float, rng: np.random.Generator, device=None):
     """U diag(s) V^T with s_i = cond^(i/(n-1)); det = prod s_i > 0, so
-    log|det| = n ln(cond) / 2 in closed form."""
-    U = haar_orthogonal(n, rng)
-    V = haar_orthogonal(n, rng)
+    log|det| = n ln(cond) / 2 in closed form.  ``device``: build it there
+    with torch (returns a torch tensor)."""
+    U = haar_orthogonal(n, rng, device)
+    V = haar_orthogonal(n, rng, device)
     s = cond ** (np.arange(n) / max(n - 1, 1))
+    if device is not None:
+        import torch
+        st = torch.from_numpy(s).to(device)
+        return (U * st[None, :]) @ V.T.contiguous()
     return (U * s[None, :]) @ V.T
 
 
-def single_conditioned(n: int = 8192, cond: float = 1e6, offset: int = 0) -> np.ndarray:
-    return conditioned(n, cond, rng_for(4, offset))
+def single_conditioned(n: int = 8192, cond: float = 1e6, offset: int = 0, device=None):
+    return conditioned(n, cond, rng_for(4, offset), device)
 
 
 def batch_conditioned(batch: int = 20_000, nmin: int = 32, nmax: int = 512,
