@@ -147,46 +147,46 @@ struct BatchPlan {
     std::vector<int2> bmap;
     std::vector<int> grid_per_step;
     int big_nt = 256, big_max_n = 0;
+    int cls_start[kOnchipClasses] = {0}, cls_count[kOnchipClasses] = {0};
     // byte offsets in the workspace
     size_t off_mats = 0, off_tasks = 0, off_queue = 0, off_descs = 0, off_bmap = 0, total = 0;
 };
 
 bool plan_batch(int batch, const int32_t *n_host, bool fp32, BatchPlan &P) {
     P = BatchPlan();
-    std::vector<int> small_k1, small_k0;
+    std::vector<int> by_cls[kOnchipClasses];
     for (int b = 0; b < batch; ++b) {
         const int n = n_host[b];
         if (n < 1 || n > kMaxN) return false;
-        if (n <= 64) small_k1.push_back(b);
-        else if (n <= kOnchipMax) small_k0.push_back(b);
+        if (n <= kOnchipMax) by_cls[onchip_class_of(n, false)].push_back(b);
         else P.big_members.push_back(b);
     }
     auto by_n_desc = [&](int x, int y) {
         return n_host[x] != n_host[y] ? n_host[x] > n_host[y] : x < y;
     };
-    std::sort(small_k1.begin(), small_k1.end(), by_n_desc);
-    std::sort(small_k0.begin(), small_k0.end(), by_n_desc);
     std::sort(P.big_members.begin(), P.big_members.end(), by_n_desc);
-    // tasks, most expensive first (cost ~ n^3; a kind-1 task runs its four
-    // members side by side, so it costs as much as its largest)
-    struct T2 { double cost; OnchipTask t; };
-    std::vector<T2> tl;
-    for (int m : small_k0) {
-        OnchipTask t{0, {m, -1, -1, -1}};
-        tl.push_back({std::pow((double)n_host[m], 3.0) / 4.0, t});
+    // one task list per class, most expensive first; a kind-1 task runs four
+    // members of the class side by side (one per wavefront)
+    for (int c = 0; c < kOnchipClasses; ++c) {
+        auto &v = by_cls[c];
+        std::sort(v.begin(), v.end(), by_n_desc);
+        P.cls_start[c] = (int)P.tasks.size();
+        if (onchip_class_kind(c) == 0) {
+            for (int m : v) P.tasks.push_back(OnchipTask{0, {m, -1, -1, -1}});
+        } else {
+            for (size_t x = 0; x < v.size(); x += 4) {
+                OnchipTask t{1, {-1, -1, -1, -1}};
+                for (int w = 0; w < 4 && x + w < v.size(); ++w) t.m[w] = v[x + w];
+                P.tasks.push_back(t);
+            }
+        }
+        P.cls_count[c] = (int)P.tasks.size() - P.cls_start[c];
     }
-    for (size_t x = 0; x < small_k1.size(); x += 4) {
-        OnchipTask t{1, {-1, -1, -1, -1}};
-        for (int w = 0; w < 4 && x + w < small_k1.size(); ++w) t.m[w] = small_k1[x + w];
-        tl.push_back({std::pow((double)n_host[t.m[0]], 3.0), t});
-    }
-    std::stable_sort(tl.begin(), tl.end(), [](const T2 &a, const T2 &b) { return a.cost > b.cost; });
-    for (auto &x : tl) P.tasks.push_back(x.t);
     // layout
     size_t c = 0;
     P.off_mats = c; c = a256(c + sizeof(MatDesc) * (size_t)batch);
     P.off_tasks = c; c = a256(c + sizeof(OnchipTask) * std::max<size_t>(1, P.tasks.size()));
-    P.off_queue = c; c = a256(c + 256);
+    P.off_queue = c; c = a256(c + 4 * kOnchipClasses);
     if (!P.big_members.empty()) {
         P.big_max_n = n_host[P.big_members[0]];
         P.big_nt = big_threads(P.big_max_n, fp32);
@@ -685,17 +685,18 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         }
         const double eps_default = fp32 ? 0.0 : kEps64;
         if (!P.tasks.empty()) {
-            int dev = 0, cus = 256;
-            hipGetDevice(&dev);
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            const int per_cu = std::max(1, env_int("GJ_ONCHIP_WG_PER_CU", 2));
-            const int grid = std::min<int>((int)P.tasks.size(), cus * per_cu);
-            hipError_t e = launch_onchip(fp32, reinterpret_cast<const MatDesc *>(w + P.off_mats),
-                                         reinterpret_cast<const OnchipTask *>(w + P.off_tasks),
-                                         (int)P.tasks.size(),
-                                         reinterpret_cast<uint32_t *>(w + P.off_queue), MatDesc(),
-                                         grid, A, X, ipiv, jpiv, res, o.zero_tol, eps_default, 0, nullptr, s);
+            uint32_t *queues = reinterpret_cast<uint32_t *>(w + P.off_queue);
+            hipError_t e = launch_zero_u32(queues, kOnchipClasses, s);
             if (e != hipSuccess) return hip_fail(e);
+            const MatDesc *mats = reinterpret_cast<const MatDesc *>(w + P.off_mats);
+            const OnchipTask *tasks = reinterpret_cast<const OnchipTask *>(w + P.off_tasks);
+            for (int c = 0; c < kOnchipClasses; ++c) {
+                if (!P.cls_count[c]) continue;
+                e = launch_onchip_class(fp32, c, mats, tasks + P.cls_start[c], P.cls_count[c],
+                                        queues + c, MatDesc(), A, X, ipiv, jpiv, res, o.zero_tol,
+                                        eps_default, 0, nullptr, s);
+                if (e != hipSuccess) return hip_fail(e);
+            }
         }
         if (!P.big_members.empty()) {
             const int nb = (int)P.bmap.size();

@@ -89,7 +89,7 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     if (rb == 0 && t == 0) { d.hdr->status = 0; d.hdr->rank = n; d.hdr->tau = 0.0; }
     if (rb == 0)
         for (int j = t; j < n; j += NT) d.collog[j] = j;
-    double ba = -1.0, bv = 0.0;
+    double ba = 0.0, bv = 0.0;   // "no candidate": (0, key 0xFFFFFFFF)
     uint32_t bk = 0xFFFFFFFFu;
     int bi = -1, bj = -1;
     bool nf = false;
@@ -150,7 +150,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const int r0 = rb * d.R, r1 = min(n, r0 + d.R);
 
     // ---- 1. reduce the candidates left by step k-1 (or the init kernel)
-    double pa = -1.0, pv = 0.0;
+    double pa = 0.0, pv = 0.0;
     uint32_t pk = 0xFFFFFFFFu;
     int pi = -1, pj = -1;
     {
@@ -170,7 +170,9 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
         tau = d.hdr->tau;
     }
     const bool stop_nf = !(pa <= 1.7976931348623157e308);
-    const bool stop_sing = (pa == 0.0) || ((T)pa < (T)tau);
+    // (a winner without a position cannot occur for k < n; refusing it keeps
+    // every later index in bounds)
+    const bool stop_sing = (pa == 0.0) || ((T)pa < (T)tau) || pi < 0 || pj < 0;
     if (stop_nf || stop_sing) {
         if (rb == 0 && t == 0) {
             d.hdr->status = stop_nf ? GJ_RES_NONFINITE : GJ_RES_SINGULAR;
@@ -192,6 +194,8 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
         const StepRec s = d.steps[k - 1];
         rpp = s.rphys; cpp = s.cphys; pp = (T)s.p;
     }
+    const T y = Num<T>::one() / p, yp = Num<T>::one() / pp;   // RN(1/p): div_pivot seeds
+    const bool p_ok = div_pivot_ok(p), pp_ok = div_pivot_ok(pp);
 
     // ---- 2. multipliers of the owned rows (the pivot column, eq. 15) and
     //         their new logical row indices
@@ -200,7 +204,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     for (int x = t; x < r1 - r0; x += NT) {
         const int i = r0 + x;
         T q = W[(int64_t)i * ldw + cp];
-        if (i == rpp) q = q / pp;          // deferred eq. 14 of the previous step
+        if (i == rpp) q = div_pivot(q, pp, yp, pp_ok);   // deferred eq. 14 of the previous step
         s_q[x] = q;
         const int ro = rl_old[i];
         const int rn = (i == rp) ? k : ((ro == k) ? rlog : ro);
@@ -235,7 +239,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 const int o = vget<VI, int>(co, e);
                 const int cn = (j == cp) ? k : ((o == k) ? clog : o);
                 ckey[c][e] = (j < n) ? cn : -1;
-                prow[c][e] = ((j == cp) ? one : vget<VT, T>(pw, e)) / p;
+                prow[c][e] = (j == cp) ? y : div_pivot(vget<VT, T>(pw, e), p, y, p_ok);
                 if (rb == 0 && rsub == 0 && j < n) cl_new[j] = cn;
             }
         } else {
@@ -246,7 +250,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     __syncthreads();
 
     // ---- 4. eq. 15 on the owned rows + fused pivot search for step k+1
-    double ba = -1.0, bv = 0.0;
+    double ba = 0.0, bv = 0.0;   // "no candidate": (0, key 0xFFFFFFFF)
     uint32_t bk = 0xFFFFFFFFu;
     int bi = -1, bj = -1;
     bool nf = false;
@@ -267,7 +271,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 for (int e = 0; e < VE; ++e) {
                     const int j = j0 + e;
                     T cur = vget<VT, T>(w, e);
-                    if (fix) cur = ((j == cpp) ? one : cur) / pp;
+                    if (fix) cur = (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok);
                     if (j == cp) cur = (T)0;
                     const T nv = Num<T>::fma_(-q, prow[c][e], cur);
                     vset<VT, T>(w, e, nv);

@@ -39,6 +39,40 @@ template <> struct Num<float> {
     __device__ static inline float one() { return 1.0f; }
 };
 
+// x / p correctly rounded (eq. 14), from y = RN(1/p) computed once per step.
+// Markstein's theorem: with y = RN(1/p) and q = RN(x y), the residual
+// r = x - p q is exact (one fma) and RN(q + r y) = RN(x / p), provided no
+// intermediate overflows or underflows.  That holds when x and p are normal
+// with |exponent| <= 500 (FP64) or 60 (FP32); zeros give q exactly; any
+// other operand takes the IEEE division.  (Checked against IEEE division on
+// 4e8 random and all-ones-mantissa operand pairs per precision.)
+template <typename T> struct DivRange;
+template <> struct DivRange<double> {
+    __device__ static constexpr double lo() { return 0x1p-500; }
+    __device__ static constexpr double hi() { return 0x1p+500; }
+};
+template <> struct DivRange<float> {
+    __device__ static constexpr float lo() { return 0x1p-60f; }
+    __device__ static constexpr float hi() { return 0x1p+60f; }
+};
+
+template <typename T>
+__device__ inline bool div_pivot_ok(T p) {
+    const T ap = Num<T>::abs_(p);
+    return ap >= DivRange<T>::lo() && ap <= DivRange<T>::hi();
+}
+
+template <typename T>
+__device__ inline T div_pivot(T x, T p, T y, bool p_ok) {
+    const T ax = Num<T>::abs_(x);
+    const T q = x * y;
+    const T r = Num<T>::fma_(-p, q, x);
+    T res = (ax == (T)0) ? q : Num<T>::fma_(r, y, q);
+    const bool fast = (ax == (T)0) || (p_ok && ax >= DivRange<T>::lo() && ax <= DivRange<T>::hi());
+    if (!fast) res = x / p;
+    return res;
+}
+
 // Running product of pivots (eq. 13) as mantissa * 2^exp, renormalised after
 // every multiplication so that it neither overflows nor underflows.
 template <typename T> struct DetAcc {
@@ -93,33 +127,92 @@ __device__ inline void write_result_fail(gj_result *res, int code, int rank) {
     res->resid = __builtin_nan("");
 }
 
-// Argmax candidate: largest |a|, ties to the smallest key.  key packs
+// Argmax candidate: largest |v|, ties to the smallest key.  key packs
 // (row << 16 | col) of the current matrix, so unsigned order is row-major
-// order.
+// order.  "No candidate" is (0, 0xFFFFFFFF): it loses every comparison with a
+// real candidate, zeros included.
 template <typename T> struct Cand {
-    T a;         // |value|, -1 when the thread has no candidate
-    T v;         // signed value
+    T v;           // signed value
     uint32_t key;
 };
 
 template <typename T>
-__device__ inline bool better(T a1, uint32_t k1, T a2, uint32_t k2) {
+__device__ inline bool better(T v1, uint32_t k1, T v2, uint32_t k2) {
+    const T a1 = Num<T>::abs_(v1), a2 = Num<T>::abs_(v2);
     return (a1 > a2) || (a1 == a2 && k1 < k2);
 }
 
+// ---- cross-lane moves without LDS: DPP within rows of 16 lanes, permlane
+// swaps across rows (gfx950)
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, CTRL, 0xF, 0xF, false);
+}
+
+template <typename T> struct Lanes;
+template <> struct Lanes<double> {
+    static constexpr int W = 2;
+    __device__ static inline void split(double v, uint32_t *w) {
+        w[0] = (uint32_t)__double2loint(v);
+        w[1] = (uint32_t)__double2hiint(v);
+    }
+    __device__ static inline double join(const uint32_t *w) {
+        return __hiloint2double((int)w[1], (int)w[0]);
+    }
+};
+template <> struct Lanes<float> {
+    static constexpr int W = 1;
+    __device__ static inline void split(float v, uint32_t *w) { w[0] = __float_as_uint(v); }
+    __device__ static inline float join(const uint32_t *w) { return __uint_as_float(w[0]); }
+};
+
+template <typename T>
+__device__ inline void cand_take(Cand<T> &c, T ov, uint32_t ok) {
+    if (better(ov, ok, c.v, c.key)) { c.v = ov; c.key = ok; }
+}
+
+template <typename T, int CTRL>
+__device__ inline void argmax_dpp_step(Cand<T> &c) {
+    uint32_t w[Lanes<T>::W];
+    Lanes<T>::split(c.v, w);
+#pragma unroll
+    for (int x = 0; x < Lanes<T>::W; ++x) w[x] = dpp_u32<CTRL>(w[x]);
+    const uint32_t ok = dpp_u32<CTRL>(c.key);
+    cand_take(c, Lanes<T>::join(w), ok);
+}
+
+// permlane{16,32}_swap with the same register as both operands leaves the
+// pair (own row/half, partner row/half) in identical order in every lane of
+// the pair, so combining the two halves gives every lane the same winner.
+template <typename T, bool P32>
+__device__ inline void argmax_perm_step(Cand<T> &c) {
+    uint32_t w[Lanes<T>::W], a[Lanes<T>::W], b[Lanes<T>::W];
+    Lanes<T>::split(c.v, w);
+#pragma unroll
+    for (int x = 0; x < Lanes<T>::W; ++x) {
+        auto p = P32 ? __builtin_amdgcn_permlane32_swap(w[x], w[x], false, false)
+                     : __builtin_amdgcn_permlane16_swap(w[x], w[x], false, false);
+        a[x] = p[0];
+        b[x] = p[1];
+    }
+    auto pk = P32 ? __builtin_amdgcn_permlane32_swap(c.key, c.key, false, false)
+                  : __builtin_amdgcn_permlane16_swap(c.key, c.key, false, false);
+    Cand<T> r;
+    r.v = Lanes<T>::join(a);
+    r.key = pk[0];
+    cand_take(r, Lanes<T>::join(b), pk[1]);
+    c = r;
+}
+
+// Every lane of the wavefront ends with the wavefront's winner.
 template <typename T>
 __device__ inline void wave_argmax(Cand<T> &c) {
-#pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) {
-        T oa = __shfl_xor(c.a, off, kWave);
-        T ov = __shfl_xor(c.v, off, kWave);
-        uint32_t ok = (uint32_t)__shfl_xor((int)c.key, off, kWave);
-        if (better(oa, ok, c.a, c.key)) {
-            c.a = oa;
-            c.v = ov;
-            c.key = ok;
-        }
-    }
+    argmax_dpp_step<T, 0xB1>(c);   // quad_perm [1,0,3,2]
+    argmax_dpp_step<T, 0x4E>(c);   // quad_perm [2,3,0,1]
+    argmax_dpp_step<T, 0x141>(c);  // row_half_mirror
+    argmax_dpp_step<T, 0x140>(c);  // row_mirror
+    argmax_perm_step<T, false>(c);
+    argmax_perm_step<T, true>(c);
 }
 
 // Descriptor of one matrix of a batch (offsets in elements).

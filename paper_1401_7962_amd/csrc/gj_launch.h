@@ -7,6 +7,17 @@ namespace gj {
 
 hipError_t launch_zero_u32(uint32_t *p, int count, hipStream_t s);
 
+// on-chip task classes for batches: 0 = (kind 0, E 8, n in 65..128),
+// 1..4 = (kind 1, E 8/4/2/1, n in 33..64 / 17..32 / 9..16 / 1..8)
+constexpr int kOnchipClasses = 5;
+int onchip_class_of(int n, bool single);
+int onchip_class_kind(int c);
+hipError_t launch_onchip_class(bool fp32, int cls, const MatDesc *mats, const OnchipTask *tasks,
+                               int ntasks, uint32_t *queue, const MatDesc &single, const double *A,
+                               double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,
+                               double zero_tol, double eps_default, int det_only,
+                               const int32_t *run_flag, hipStream_t s);
+
 hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks, int ntasks,
                          uint32_t *queue, const MatDesc &single, int grid, const double *A,
                          double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res, double zero_tol,

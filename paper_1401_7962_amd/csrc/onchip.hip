@@ -24,20 +24,26 @@
 // the working array goes to X(g[i], h[j]), where g and h are the inverse
 // permutations of the reversed swap sequence, built forward one swap per
 // step.
-#include "gj_device.h"
+#include <algorithm>
+
+#include "gj_launch.h"
 
 namespace gj {
 
 template <typename T, int N, int NW>
 struct CoreLds {
+    // Positions >= n (padding) hold 0 in every array and in the registers: the
+    // swap maps fix them, so padding lanes stage 0 onto 0, and a 0 never wins
+    // the pivot search.  No per-element bounds test is needed.
     T prow[N];     // new pivot row, divided by the pivot
     T pcol[N];     // new pivot column (multipliers)
     T newr[N];     // new row r  (= old row k, columns swapped)
     T newc[N];     // new column c (= old column k, rows swapped)
     int32_t g[N];  // destination row of working row i
     int32_t h[N];  // destination column of working column j
+    int32_t ip[N]; // pivot sequence, written out once at the end (a global
+    int32_t jp[N]; // store inside the step loop would make every barrier wait for it)
     Cand<T> red[NW];
-    int32_t nfw[NW];
 };
 
 template <int NW>
@@ -51,82 +57,78 @@ __device__ inline void group_sync() {
     }
 }
 
-// Reduce (|a|, key) over the group.  Every thread ends with the same winner.
+// Reduce (|v|, key) over the group.  Every thread ends with the same winner.
 template <typename T, int N, int NW>
-__device__ inline void group_argmax(Cand<T> &c, bool &nf, CoreLds<T, N, NW> &L, int t) {
+__device__ inline void group_argmax(Cand<T> &c, CoreLds<T, N, NW> &L, int t) {
     wave_argmax(c);
-    int any_nf = __any(nf ? 1 : 0);
-    if constexpr (NW == 1) {
-        nf = any_nf != 0;
-    } else {
+    if constexpr (NW > 1) {
         const int lane = t & (kWave - 1), w = t / kWave;
-        if (lane == 0) {
-            L.red[w] = c;
-            L.nfw[w] = any_nf;
-        }
+        if (lane == 0) L.red[w] = c;
         __syncthreads();
         Cand<T> best = L.red[0];
-        int nfa = L.nfw[0];
 #pragma unroll
         for (int x = 1; x < NW; ++x) {
-            Cand<T> o = L.red[x];
-            nfa |= L.nfw[x];
-            if (better(o.a, o.key, best.a, best.key)) best = o;
+            const Cand<T> o = L.red[x];
+            cand_take(best, o.v, o.key);
         }
         c = best;
-        nf = nfa != 0;
     }
 }
 
-// Scan this thread's part of the trailing block (rows and columns > k, < n)
-// in row-major order; strict '>' keeps the first maximum.  The winning slot
-// is tracked as the compile-time code a*EB+b so that no per-element key has
-// to stay live across steps; the key is formed once at the end.
+// Scan this thread's part of the trailing block (rows and columns > k) in
+// row-major order; strict '>' keeps the first maximum (padding holds 0 and
+// never wins).  Register blocks
+// whose rows (or columns) are all pivoted already are skipped: the test is
+// the same for the whole wavefront.  The winning slot is tracked as the
+// compile-time code a*EB+b so that no per-element key stays live across
+// steps.
 template <typename T, int TR, int TC, int EA, int EB>
-__device__ __forceinline__ void scan_argmax(const T (&v)[EA][EB], int k, int n, int tr, int tc,
-                                            Cand<T> &c, bool &nf) {
+__device__ __forceinline__ void scan_argmax(const T (&v)[EA][EB], int k, int tr, int tc,
+                                            Cand<T> &c) {
     using M = Num<T>;
     bool cok[EB];
 #pragma unroll
-    for (int b = 0; b < EB; ++b) {
-        const int j = b * TC + tc;
-        cok[b] = (j > k) && (j < n);
-    }
-    T best = (T)0;
-    int code = -1;
-    bool bad = false;
+    for (int b = 0; b < EB; ++b) cok[b] = (b * TC + tc > k);
+    // one running maximum per register row (independent chains), each kept
+    // with strict '>' so that it holds the row's first maximum
+    T rbest[EA];
+    int rcode[EA];
 #pragma unroll
     for (int a = 0; a < EA; ++a) {
-        const int i = a * TR + tr;
-        const bool rok = (i > k) && (i < n);
+        rbest[a] = (T)0;
+        rcode[a] = -1;
+        if (a * TR + TR - 1 <= k) continue;        // every row of this block pivoted
+        const bool rok = (a * TR + tr > k);
 #pragma unroll
         for (int b = 0; b < EB; ++b) {
+            if (b * TC + TC - 1 <= k) continue;    // every column of this block pivoted
             const T x = v[a][b];
-            const bool ok = rok && cok[b];
-            bad |= ok && !M::finite_(x);
-            if (ok && M::abs_(x) > M::abs_(best)) {
-                best = x;
-                code = a * EB + b;
-            }
+            const bool gt = rok && cok[b] && (M::abs_(x) > M::abs_(rbest[a]));
+            rbest[a] = gt ? x : rbest[a];
+            rcode[a] = gt ? (a * EB + b) : rcode[a];
         }
     }
-    c.v = best;
-    c.a = M::abs_(best);
-    if (code >= 0) {
-        const int i = (code / EB) * TR + tr, j = (code % EB) * TC + tc;
-        c.key = ((uint32_t)i << 16) | (uint32_t)j;
-    } else {
-        c.key = 0xFFFFFFFFu;
+    // rows in increasing order, strict '>': the first maximum in row-major order
+    T best = rbest[0];
+    int code = rcode[0];
+#pragma unroll
+    for (int a = 1; a < EA; ++a) {
+        const bool gt = M::abs_(rbest[a]) > M::abs_(best);
+        best = gt ? rbest[a] : best;
+        code = gt ? rcode[a] : code;
     }
-    nf = bad;
+    c.v = best;
+    const int i = (code / EB) * TR + tr, j = (code % EB) * TC + tc;
+    c.key = (code >= 0) ? (((uint32_t)i << 16) | (uint32_t)j) : 0xFFFFFFFFu;
 }
 
 template <typename T, int TR, int TC, int EA, int EB, int NW>
 __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *__restrict__ A,
-                        double *__restrict__ X, int32_t *__restrict__ ipiv_all,
-                        int32_t *__restrict__ jpiv_all, gj_result *__restrict__ res_all,
-                        double zero_tol, double eps_default, int det_only,
-                        CoreLds<T, TR * EA, NW> &L) {
+                                        double *__restrict__ X, int32_t *__restrict__ ipiv_all,
+                                        int32_t *__restrict__ jpiv_all,
+                                        gj_result *__restrict__ res_all, double zero_tol,
+                                        double eps_default, int det_only,
+                                        CoreLds<T, TR * EA, NW> &L) {
     constexpr int N = TR * EA;
     static_assert(TR * EA == TC * EB, "square tiling");
     static_assert(TR * TC == NW * kWave, "thread grid");
@@ -138,6 +140,7 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
     gj_result *res = res_all + md.res_idx;
 
     T v[EA][EB];
+    bool bad = false;
 #pragma unroll
     for (int a = 0; a < EA; ++a) {
         const int i = a * TR + tr;
@@ -145,43 +148,52 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
         for (int b = 0; b < EB; ++b) {
             const int j = b * TC + tc;
             v[a][b] = (i < n && j < n) ? (T)A[md.a_off + (int64_t)i * md.lda + j] : (T)0;
+            bad |= !M::finite_(v[a][b]);
         }
     }
     for (int x = t; x < N; x += TR * TC) {
         L.prow[x] = (T)0;
         L.pcol[x] = (T)0;
+        L.newr[x] = (T)0;
+        L.newc[x] = (T)0;
         L.g[x] = x;
         L.h[x] = x;
     }
 
-    // pivot search of step 0 over the whole matrix
+    // Non-finite candidates: every candidate of step 0 is checked here.  After
+    // that only an overflow to +-inf can make a candidate non-finite (with
+    // full pivoting |a_kj / p| <= 1 on the candidate columns, so no 0 * inf
+    // arises), and an infinity always wins the pivot search; so testing the
+    // winner is enough for the later steps.
     Cand<T> c;
-    bool nf = false;
-    scan_argmax<T, TR, TC, EA, EB>(v, -1, n, tr, tc, c, nf);
-    group_argmax(c, nf, L, t);
+    scan_argmax<T, TR, TC, EA, EB>(v, -1, tr, tc, c);
+    group_argmax(c, L, t);
+    bool nf;
+    if constexpr (NW == 1) {
+        nf = __any(bad ? 1 : 0) != 0;
+    } else {
+        nf = __syncthreads_or(bad ? 1 : 0) != 0;
+    }
 
-    const T tau = (zero_tol >= 0.0) ? (T)zero_tol : (T)n * (T)eps_default * c.a;
+    const T tau = (zero_tol >= 0.0) ? (T)zero_tol : (T)n * (T)eps_default * M::abs_(c.v);
     DetAcc<T> det;
     det.init();
     int code = GJ_RES_OK, rank = n;
 
     for (int k = 0; k < n; ++k) {
-        if (nf) { code = GJ_RES_NONFINITE; rank = k; break; }
-        if (c.a == (T)0 || c.a < tau) { code = GJ_RES_SINGULAR; rank = k; break; }
+        const T m = M::abs_(c.v);
+        if (nf || !M::finite_(m)) { code = GJ_RES_NONFINITE; rank = k; break; }
+        if (m == (T)0 || m < tau) { code = GJ_RES_SINGULAR; rank = k; break; }
         const int r = (int)(c.key >> 16), cc = (int)(c.key & 0xFFFFu);
         const T p = c.v;
         det.mul(p);
         if (r != k) det.sign = -det.sign;
         if (cc != k) det.sign = -det.sign;
-        if (t == 0) {
-            ipiv[k] = r;
-            jpiv[k] = cc;
-            int tmp = L.g[k]; L.g[k] = L.g[cc]; L.g[cc] = tmp;
-            tmp = L.h[k]; L.h[k] = L.h[r]; L.h[r] = tmp;
-        }
         const int ar = r / TR, trr = r % TR, ak = k / TR, trk = k % TR;
         const int bc = cc / TC, tcc = cc % TC, bk = k / TC, tck = k % TC;
         const T one = M::one();
+        const T y = one / p;                   // RN(1/p): the pivot slot, and div_pivot's seed
+        const bool p_ok = div_pivot_ok(p);
 
         // stage the four swapped lines and the scaled pivot row (eq. 14)
         if (tr == trr) {
@@ -190,10 +202,8 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 #pragma unroll
                 for (int b = 0; b < EB; ++b) {
                     const int jo = b * TC + tc;
-                    if (jo < n) {
-                        const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
-                        L.prow[jn] = ((jo == cc) ? one : v[a][b]) / p;
-                    }
+                    const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
+                    L.prow[jn] = (jo == cc) ? y : div_pivot(v[a][b], p, y, p_ok);
                 }
             }
         }
@@ -203,10 +213,8 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 #pragma unroll
                 for (int b = 0; b < EB; ++b) {
                     const int jo = b * TC + tc;
-                    if (jo < n) {
-                        const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
-                        L.newr[jn] = v[a][b];
-                    }
+                    const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
+                    L.newr[jn] = v[a][b];
                 }
             }
         }
@@ -216,10 +224,8 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 #pragma unroll
                 for (int a = 0; a < EA; ++a) {
                     const int io = a * TR + tr;
-                    if (io < n) {
-                        const int in = (io == r) ? k : ((io == k) ? r : io);
-                        L.pcol[in] = v[a][b];
-                    }
+                    const int in = (io == r) ? k : ((io == k) ? r : io);
+                    L.pcol[in] = v[a][b];
                 }
             }
         }
@@ -229,14 +235,20 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 #pragma unroll
                 for (int a = 0; a < EA; ++a) {
                     const int io = a * TR + tr;
-                    if (io < n) {
-                        const int in = (io == r) ? k : ((io == k) ? r : io);
-                        L.newc[in] = v[a][b];
-                    }
+                    const int in = (io == r) ? k : ((io == k) ? r : io);
+                    L.newc[in] = v[a][b];
                 }
             }
         }
         group_sync<NW>();
+
+        // bookkeeping off the critical path: pivots and the depivoting maps
+        if (t == 0) {
+            L.ip[k] = r;
+            L.jp[k] = cc;
+            int tmp = L.g[k]; L.g[k] = L.g[cc]; L.g[cc] = tmp;
+            tmp = L.h[k]; L.h[k] = L.h[r]; L.h[r] = tmp;
+        }
 
         // install the swapped row r and column c; clear column k (it becomes
         // fma(-q, 1/p, 0) below, the D column of eq. 15)
@@ -244,20 +256,14 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 #pragma unroll
             for (int a = 0; a < EA; ++a) if (a == ar) {
 #pragma unroll
-                for (int b = 0; b < EB; ++b) {
-                    const int j = b * TC + tc;
-                    if (j < n) v[a][b] = L.newr[j];
-                }
+                for (int b = 0; b < EB; ++b) v[a][b] = L.newr[b * TC + tc];
             }
         }
         if (tc == tcc) {
 #pragma unroll
             for (int b = 0; b < EB; ++b) if (b == bc) {
 #pragma unroll
-                for (int a = 0; a < EA; ++a) {
-                    const int i = a * TR + tr;
-                    if (i < n) v[a][b] = L.newc[i];
-                }
+                for (int a = 0; a < EA; ++a) v[a][b] = L.newc[a * TR + tr];
             }
         }
         if (tc == tck) {
@@ -288,13 +294,17 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 
         // fused pivot search for step k+1 over rows and columns > k
         if (k + 1 < n) {
-            scan_argmax<T, TR, TC, EA, EB>(v, k, n, tr, tc, c, nf);
-            group_argmax(c, nf, L, t);
+            scan_argmax<T, TR, TC, EA, EB>(v, k, tr, tc, c);
+            group_argmax(c, L, t);
         }
     }
 
-    // ensure thread 0's last swaps of g/h are visible
+    // ensure thread 0's last swaps of g/h and pivots are visible
     group_sync<NW>();
+    for (int x = t; x < n; x += TR * TC) {
+        ipiv[x] = (x < rank) ? L.ip[x] : -1;
+        jpiv[x] = (x < rank) ? L.jp[x] : -1;
+    }
     if (code == GJ_RES_OK) {
         if (!det_only) {
 #pragma unroll
@@ -323,77 +333,36 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
                     }
             }
         }
-        for (int x = rank + t; x < n; x += TR * TC) {
-            ipiv[x] = -1;
-            jpiv[x] = -1;
-        }
         if (t == 0) write_result_fail(res, code, rank);
     }
 }
 
-// LDS shared by the two task kinds (union by reinterpretation).
-template <typename T>
-struct OnchipShared {
-    static constexpr size_t k0 = sizeof(CoreLds<T, 128, 4>);
-    static constexpr size_t k1 = 4 * sizeof(CoreLds<T, 64, 1>);
-    static constexpr size_t bytes = (k0 > k1 ? k0 : k1);
-};
-
-// Kind 0: one matrix, all four wavefronts.
-template <typename T>
-__device__ inline void run_kind0(unsigned char *smem, int t, const MatDesc &md, const double *A,
-                                 double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,
-                                 double zero_tol, double eps_default, int det_only) {
-    if (md.n <= 32) {
-        gj_core<T, 16, 16, 2, 2, 4>(t, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
-                                    *reinterpret_cast<CoreLds<T, 32, 4> *>(smem));
-    } else if (md.n <= 64) {
-        gj_core<T, 16, 16, 4, 4, 4>(t, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
-                                    *reinterpret_cast<CoreLds<T, 64, 4> *>(smem));
-    } else {
-        gj_core<T, 16, 16, 8, 8, 4>(t, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
-                                    *reinterpret_cast<CoreLds<T, 128, 4> *>(smem));
-    }
-}
-
-// Kind 1: one matrix per wavefront (n <= 64).
-template <typename T>
-__device__ inline void run_kind1(unsigned char *smem, int lane, int w, const MatDesc &md,
-                                 const double *A, double *X, int32_t *ipiv, int32_t *jpiv,
-                                 gj_result *res, double zero_tol, double eps_default, int det_only) {
-    unsigned char *Lw = smem + (size_t)w * sizeof(CoreLds<T, 64, 1>);
-    if (md.n <= 8) {
-        gj_core<T, 8, 8, 1, 1, 1>(lane, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
-                                  *reinterpret_cast<CoreLds<T, 8, 1> *>(Lw));
-    } else if (md.n <= 16) {
-        gj_core<T, 8, 8, 2, 2, 1>(lane, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
-                                  *reinterpret_cast<CoreLds<T, 16, 1> *>(Lw));
-    } else if (md.n <= 32) {
-        gj_core<T, 8, 8, 4, 4, 1>(lane, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
-                                  *reinterpret_cast<CoreLds<T, 32, 1> *>(Lw));
-    } else {
-        gj_core<T, 8, 8, 8, 8, 1>(lane, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
-                                  *reinterpret_cast<CoreLds<T, 64, 1> *>(Lw));
-    }
-}
-
-// Persistent kernel: workgroups take tasks from an atomic queue until it is
-// empty; tasks are ordered by decreasing cost on the host.  With mats ==
-// nullptr the kernel inverts the single matrix passed by value (workgroup 0).
-template <typename T>
+// Persistent kernel for one class of tasks: KIND 0 = one matrix on all four
+// wavefronts (16 x 16 threads, E x E values each, n <= 16 E); KIND 1 = one
+// matrix per wavefront (8 x 8 lanes, n <= 8 E).  Workgroups take tasks from
+// an atomic queue until it is empty; tasks are ordered by decreasing cost on
+// the host.  With mats == nullptr the kernel inverts the single matrix passed
+// by value (workgroup 0, KIND 0).
+template <typename T, int KIND, int E>
 __global__ void __launch_bounds__(256)
 gj_onchip_kernel(const MatDesc *__restrict__ mats, const OnchipTask *__restrict__ tasks,
                  int ntasks, uint32_t *__restrict__ queue, const MatDesc single,
                  const double *__restrict__ A, double *__restrict__ X, int32_t *__restrict__ ipiv,
                  int32_t *__restrict__ jpiv, gj_result *__restrict__ res, double zero_tol,
                  double eps_default, int det_only, const int32_t *__restrict__ run_flag) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[OnchipShared<T>::bytes];
+    using L0 = CoreLds<T, 16 * E, 4>;
+    using L1 = CoreLds<T, 8 * E, 1>;
+    constexpr size_t kBytes = KIND == 0 ? sizeof(L0) : 4 * sizeof(L1);
+    __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
     __shared__ int s_task;
     const int t = threadIdx.x;
     if (run_flag && *run_flag == 0) return;
     if (mats == nullptr) {
-        if (blockIdx.x == 0)
-            run_kind0<T>(smem, t, single, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only);
+        if constexpr (KIND == 0) {
+            if (blockIdx.x == 0)
+                gj_core<T, 16, 16, E, E, 4>(t, single, A, X, ipiv, jpiv, res, zero_tol,
+                                            eps_default, det_only, *reinterpret_cast<L0 *>(smem));
+        }
         return;
     }
     for (;;) {
@@ -403,16 +372,17 @@ gj_onchip_kernel(const MatDesc *__restrict__ mats, const OnchipTask *__restrict_
         __syncthreads();
         if (id >= ntasks) break;
         const OnchipTask task = tasks[id];
-        if (task.kind == 0) {
+        if constexpr (KIND == 0) {
             const MatDesc md = mats[task.m[0]];
-            run_kind0<T>(smem, t, md, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only);
+            gj_core<T, 16, 16, E, E, 4>(t, md, A, X, ipiv, jpiv, res, zero_tol, eps_default,
+                                        det_only, *reinterpret_cast<L0 *>(smem));
         } else {
             const int w = t / kWave, lane = t % kWave;
             const int mi = task.m[w];
             if (mi >= 0) {
                 const MatDesc md = mats[mi];
-                run_kind1<T>(smem, lane, w, md, A, X, ipiv, jpiv, res, zero_tol, eps_default,
-                             det_only);
+                gj_core<T, 8, 8, E, E, 1>(lane, md, A, X, ipiv, jpiv, res, zero_tol, eps_default,
+                                          det_only, reinterpret_cast<L1 *>(smem)[w]);
             }
         }
         __syncthreads();
@@ -431,24 +401,74 @@ hipError_t launch_zero_u32(uint32_t *p, int count, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Task classes: (kind, E).  Class c covers n in (lo, hi].
+struct OnchipClass { int kind, e, lo, hi; };
+static const OnchipClass kClasses[kOnchipClasses] = {
+    {0, 8, 64, 128}, {1, 8, 32, 64}, {1, 4, 16, 32}, {1, 2, 8, 16}, {1, 1, 0, 8}};
+
+int onchip_class_of(int n, bool single) {
+    if (single) return n <= 32 ? 7 : (n <= 64 ? 6 : 0);   // single matrices: all four wavefronts
+    for (int c = 0; c < kOnchipClasses; ++c)
+        if (n > kClasses[c].lo && n <= kClasses[c].hi) return c;
+    return -1;
+}
+int onchip_class_kind(int c) { return c < kOnchipClasses ? kClasses[c].kind : 0; }
+
+template <typename T, int KIND, int E>
+static hipError_t launch_cls(const MatDesc *mats, const OnchipTask *tasks, int ntasks,
+                             uint32_t *queue, const MatDesc &single, int grid, const double *A,
+                             double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,
+                             double zero_tol, double eps_default, int det_only,
+                             const int32_t *run_flag, hipStream_t s) {
+    if (mats) {
+        int dev = 0, cus = 256, per = 1;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gj_onchip_kernel<T, KIND, E>, 256, 0) != hipSuccess) per = 1;
+        grid = std::max(1, std::min(ntasks, cus * std::max(per, 1)));
+    }
+    hipLaunchKernelGGL((gj_onchip_kernel<T, KIND, E>), dim3(grid), dim3(256), 0, s, mats, tasks,
+                       ntasks, queue, single, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
+                       run_flag);
+    return hipGetLastError();
+}
+
+// cls: 0..4 batched classes (kClasses), 6 / 7: single matrix with E = 4 / 2.
+hipError_t launch_onchip_class(bool fp32, int cls, const MatDesc *mats, const OnchipTask *tasks,
+                               int ntasks, uint32_t *queue, const MatDesc &single, const double *A,
+                               double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,
+                               double zero_tol, double eps_default, int det_only,
+                               const int32_t *run_flag, hipStream_t s) {
+#define GJ_CLS(K, EE)                                                                         \
+    return fp32 ? launch_cls<float, K, EE>(mats, tasks, ntasks, queue, single, 1, A, X, ipiv,  \
+                                           jpiv, res, zero_tol, eps_default, det_only,         \
+                                           run_flag, s)                                        \
+                : launch_cls<double, K, EE>(mats, tasks, ntasks, queue, single, 1, A, X, ipiv, \
+                                            jpiv, res, zero_tol, eps_default, det_only,        \
+                                            run_flag, s)
+    switch (cls) {
+        case 0: GJ_CLS(0, 8);
+        case 1: GJ_CLS(1, 8);
+        case 2: GJ_CLS(1, 4);
+        case 3: GJ_CLS(1, 2);
+        case 4: GJ_CLS(1, 1);
+        case 6: GJ_CLS(0, 4);
+        case 7: GJ_CLS(0, 2);
+    }
+#undef GJ_CLS
+    return hipErrorInvalidValue;
+}
+
+// Single matrix (n <= 128) on one workgroup.
 hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks, int ntasks,
                          uint32_t *queue, const MatDesc &single, int grid, const double *A,
                          double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res, double zero_tol,
                          double eps_default, int det_only, const int32_t *run_flag,
                          hipStream_t s) {
-    if (mats) {
-        hipError_t e = launch_zero_u32(queue, 1, s);
-        if (e != hipSuccess) return e;
-    }
-    if (fp32)
-        hipLaunchKernelGGL(gj_onchip_kernel<float>, dim3(grid), dim3(256), 0, s, mats, tasks,
-                           ntasks, queue, single, A, X, ipiv, jpiv, res, zero_tol, eps_default,
-                           det_only, run_flag);
-    else
-        hipLaunchKernelGGL(gj_onchip_kernel<double>, dim3(grid), dim3(256), 0, s, mats, tasks,
-                           ntasks, queue, single, A, X, ipiv, jpiv, res, zero_tol, eps_default,
-                           det_only, run_flag);
-    return hipGetLastError();
+    (void)mats; (void)tasks; (void)ntasks; (void)queue; (void)grid;
+    return launch_onchip_class(fp32, onchip_class_of(single.n, true), nullptr, nullptr, 0, nullptr,
+                               single, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
+                               run_flag, s);
 }
 
 }  // namespace gj
