@@ -261,6 +261,7 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
         md.lda = (int32_t)lda;
         md.ldx = (int32_t)(det_only ? n : ldx);
         md.res_idx = 0;
+        md.run = nullptr;
         if (o.events && o.events[0]) {
             hipError_t e = hipEventRecord((hipEvent_t)o.events[0], s);
             if (e != hipSuccess) return hip_fail(e);
@@ -351,13 +352,14 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
     int32_t *rows = reinterpret_cast<int32_t *>(w + L.rows);
     int32_t *cols = reinterpret_cast<int32_t *>(w + L.cols);
     int32_t *bpiv = reinterpret_cast<int32_t *>(w + L.bpiv);
-    const int det = det_only ? 1 : 1;  // the refined path always returns the FP64 determinant
+    const int nparts = gemm_tiles(n, n);
+    const int row_blocks = std::min(n, 1024);
 
     // 1. FP32 elimination (zero threshold 0): X0 in X, pivots, FP32 status
     BigDesc d32;
     std::memset(&d32, 0, sizeof(d32));
     if (n <= kOnchipMax) {
-        MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0};
+        MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0, nullptr};
         if (o.events && o.events[0]) GJ_TRY(hipEventRecord((hipEvent_t)o.events[0], s));
         GJ_TRY(launch_onchip(true, nullptr, nullptr, 0, nullptr, md, 1, A, det_only ? nullptr : X,
                              ipiv, jpiv, res, 0.0, 0.0, det_only ? 1 : 0, nullptr, s));
@@ -370,10 +372,23 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         GJ_TRY(launch_big(true, nt, nullptr, nullptr, d32, nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, 0.0, 0.0, det_only ? 1 : 0, o.events, nullptr, s));
     }
-    GJ_TRY(launch_refine_start(res, ctl, s));
+    GJ_TRY(launch_refine_bind(ctl, res, pr, nparts, s));
+    GJ_TRY(launch_refine_start(ctl, 1, s));
+
+    RefMember m;
+    std::memset(&m, 0, sizeof(m));
+    m.A = A; m.lda = lda; m.X = X; m.ldx = ldx; m.Xw = Xw; m.B = R;
+    m.ipiv = ipiv; m.jpiv = jpiv;
+    if (n <= kOnchipMax) {
+        m.rows = rows; m.cols = cols; m.rows_buf = rows; m.cols_buf = cols;
+    } else {
+        m.rows = d32.rowphys; m.cols = d32.colphys;
+    }
+    m.blockres = blockres;
+    m.n = n;
+    m.nblocks = (n + kDetBlock - 1) / kDetBlock;
 
     // 2. Newton-Schulz: R = I - A X; X' = X + X R; keep while ||R||_F drops
-    const int nparts = gemm_tiles(n, n);
     if (!det_only) {
         GemmArgs g;
         std::memset(&g, 0, sizeof(g));
@@ -382,7 +397,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         g.alpha = -1.0; g.beta = 0.0; g.gamma = 1.0;
         g.norm_partials = pr; g.run_flag = ctl_run_ns(ctl);
         GJ_TRY(launch_gemm_f64(g, s));
-        GJ_TRY(launch_refine_resid0(pr, nparts, ctl, s));
+        GJ_TRY(launch_refine_resid0(ctl, 1, s));
         for (int it = 1; it <= o.max_refine_iters; ++it) {
             double *Xs = ((it - 1) & 1) ? Xw : X;
             double *Xd = (it & 1) ? Xw : X;
@@ -397,17 +412,17 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
             GemmArgs r2 = g;
             r2.B = Xd; r2.ldb = ldd;
             GJ_TRY(launch_gemm_f64(r2, s));
-            GJ_TRY(launch_refine_after_update(pr, nparts, ctl, it, o.max_refine_iters, kStall, s));
+            GJ_TRY(launch_refine_after_update(ctl, 1, it, o.max_refine_iters, kStall, s));
         }
-        GJ_TRY(launch_refine_finish(ctl, kAcceptResid, det, s));
-        GJ_TRY(launch_copy_flagged(Xw, n, X, ldx, n, ctl_copy_back(ctl), s));
+        GJ_TRY(launch_refine_finish(ctl, 1, kAcceptResid, 1, s));
+        GJ_TRY(launch_copy_back(nullptr, m, ctl, 1, row_blocks, s));
     } else {
-        GJ_TRY(launch_refine_finish(ctl, __builtin_inf(), det, s));
+        GJ_TRY(launch_refine_finish(ctl, 1, __builtin_inf(), 1, s));
     }
 
     // 3. fallback: the plain FP64 elimination, only when flagged
     if (n <= kOnchipMax) {
-        MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0};
+        MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0, nullptr};
         GJ_TRY(launch_onchip(false, nullptr, nullptr, 0, nullptr, md, 1, A, det_only ? nullptr : X,
                              ipiv, jpiv, res, o.zero_tol, kEps64, det_only ? 1 : 0,
                              ctl_run_fallback(ctl), s));
@@ -420,30 +435,23 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
                           det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
                           ctl_run_fallback(ctl), s));
     }
-    GJ_TRY(launch_fallback_mark(res, ctl, s));
+    GJ_TRY(launch_fallback_mark(ctl, 1, s));
 
     // 4. FP64 determinant: permute A with the FP32 order, block elimination
     const int32_t *fdet = ctl_run_det(ctl);
-    const int32_t *prow = rows, *pcol = cols;
-    if (n <= kOnchipMax) {
-        GJ_TRY(launch_perms_from_pivots(ipiv, jpiv, n, rows, cols, fdet, s));
-    } else {
-        prow = d32.rowphys;
-        pcol = d32.colphys;
-    }
+    GJ_TRY(launch_perms_from_pivots(nullptr, m, ctl, 1, s));
+    GJ_TRY(launch_gather_perm(nullptr, m, ctl, 1, row_blocks, s));
     double *B = R;
-    GJ_TRY(launch_gather_perm(A, lda, prow, pcol, n, B, n, fdet, s));
-    const int nblocks = (n + kDetBlock - 1) / kDetBlock;
     for (int kb = 0, bi = 0; kb < n; kb += kDetBlock, ++bi) {
         const int nbk = std::min(kDetBlock, n - kb);
-        MatDesc md{(int64_t)kb * n + kb, 0, 0, nbk, n, kDetBlock, 0};
+        MatDesc md{(int64_t)kb * n + kb, 0, 0, nbk, n, kDetBlock, 0, nullptr};
         GJ_TRY(launch_onchip(false, nullptr, nullptr, 0, nullptr, md, 1, B, Dinv, bpiv,
                              bpiv + kDetBlock, blockres + bi, -1.0, kEps64, 0, fdet, s));
-        const int m = n - kb - nbk;
-        if (m > 0) {
+        const int mm = n - kb - nbk;
+        if (mm > 0) {
             GemmArgs g1;
             std::memset(&g1, 0, sizeof(g1));
-            g1.M = nbk; g1.N = m; g1.K = nbk;
+            g1.M = nbk; g1.N = mm; g1.K = nbk;
             g1.A = Dinv; g1.lda = kDetBlock;
             g1.B = B + (int64_t)kb * n + kb + nbk; g1.ldb = n;
             g1.D = T; g1.ldd = n;
@@ -451,7 +459,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
             GJ_TRY(launch_gemm_f64(g1, s));
             GemmArgs g2;
             std::memset(&g2, 0, sizeof(g2));
-            g2.M = m; g2.N = m; g2.K = nbk;
+            g2.M = mm; g2.N = mm; g2.K = nbk;
             g2.A = B + (int64_t)(kb + nbk) * n + kb; g2.lda = n;
             g2.B = T; g2.ldb = n;
             g2.C = B + (int64_t)(kb + nbk) * n + kb + nbk; g2.ldc = n;
@@ -460,8 +468,8 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
             GJ_TRY(launch_gemm_f64(g2, s));
         }
     }
-    GJ_TRY(launch_det_combine(blockres, nblocks, ipiv, jpiv, n, res, ctl, s));
-    GJ_TRY(launch_refine_iters(res, ctl, s));
+    GJ_TRY(launch_det_combine(nullptr, m, ctl, 1, s));
+    GJ_TRY(launch_refine_iters(ctl, 1, s));
 
     // 5. optional residual of the returned inverse
     if (o.want_resid && !det_only) {
@@ -475,6 +483,402 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         GJ_TRY(launch_sumsq(X, ldx, n, px, s));
         GJ_TRY(launch_resid(pr, nparts, pa, sumsq_blocks(n), px, sumsq_blocks(n), res, s));
     }
+    return GJ_OK;
+}
+
+// ------------------------------------------------------ batched refined
+// One grouped-GEMM problem list and its workgroup -> (problem, tile) map.
+struct GemmList {
+    std::vector<GemmArgs> probs;
+    std::vector<int2> tiles;
+    size_t off_probs = 0, off_tiles = 0;
+    void add(const GemmArgs &g) {
+        const int p = (int)probs.size();
+        probs.push_back(g);
+        const int nt = gemm_tiles(g.M, g.N);
+        for (int t = 0; t < nt; ++t) tiles.push_back(make_int2(p, t));
+    }
+};
+
+// An on-chip task set (classes as in plan_batch) over a descriptor array.
+struct OnchipSet {
+    std::vector<MatDesc> mats;
+    std::vector<OnchipTask> tasks;
+    int cls_start[kOnchipClasses] = {0}, cls_count[kOnchipClasses] = {0};
+    size_t off_mats = 0, off_tasks = 0;
+    void build() {   // tasks over all mats, grouped by class, largest first
+        std::vector<int> by_cls[kOnchipClasses];
+        for (int i = 0; i < (int)mats.size(); ++i) by_cls[onchip_class_of(mats[i].n, false)].push_back(i);
+        tasks.clear();
+        for (int c = 0; c < kOnchipClasses; ++c) {
+            auto &v = by_cls[c];
+            std::sort(v.begin(), v.end(), [&](int x, int y) {
+                return mats[x].n != mats[y].n ? mats[x].n > mats[y].n : x < y; });
+            cls_start[c] = (int)tasks.size();
+            if (onchip_class_kind(c) == 0) {
+                for (int i : v) tasks.push_back(OnchipTask{0, {i, -1, -1, -1}});
+            } else {
+                for (size_t x = 0; x < v.size(); x += 4) {
+                    OnchipTask t{1, {-1, -1, -1, -1}};
+                    for (int q = 0; q < 4 && x + q < v.size(); ++q) t.m[q] = v[x + q];
+                    tasks.push_back(t);
+                }
+            }
+            cls_count[c] = (int)tasks.size() - cls_start[c];
+        }
+    }
+};
+
+struct RefBatchPlan {
+    BatchPlan e32;                       // FP32 elimination (starts at offset 0)
+    std::vector<size_t> region, xw, r, t, dinv, parts, rows, cols, bpiv;
+    std::vector<int> nblocks, blockres_start;
+    size_t off_ctl = 0, off_mem = 0, off_blockres = 0;
+    // FP64 fallback
+    OnchipSet fb;                        // on-chip members (run flag: run_fallback)
+    std::vector<BigShape> fb_shapes;
+    std::vector<BigBufs> fb_bufs;
+    std::vector<int2> fb_bmap;
+    std::vector<int> fb_grid;
+    int fb_nt = 256;
+    size_t off_fb_descs = 0, off_fb_bmap = 0;
+    // Newton-Schulz product lists
+    GemmList r0, upd[2], res[2];
+    // determinant block steps
+    std::vector<OnchipSet> det_blocks;
+    std::vector<GemmList> det_t, det_s;
+    size_t total = 0;
+};
+
+// Byte layout only (pointers are formed at call time from the workspace base).
+bool plan_refined_batch(int batch, const int32_t *n_host, RefBatchPlan &P) {
+    if (!plan_batch(batch, n_host, true, P.e32)) return false;
+    size_t c = a256(P.e32.total);
+    P.region.resize(batch); P.xw.resize(batch); P.r.resize(batch); P.t.resize(batch);
+    P.dinv.resize(batch); P.parts.resize(batch); P.rows.resize(batch); P.cols.resize(batch);
+    P.bpiv.resize(batch); P.nblocks.resize(batch); P.blockres_start.resize(batch);
+    int nbtot = 0;
+    for (int b = 0; b < batch; ++b) {
+        const int n = n_host[b];
+        const size_t n2 = a256((size_t)n * n * 8);
+        size_t reg = 2 * n2;
+        if (n > kOnchipMax) {
+            BigShape s = big_shape(n, false, big_threads(P.e32.big_max_n, false));
+            reg = std::max(reg, big_bufs(s, false, 0).end);
+        }
+        P.region[b] = c;
+        P.xw[b] = c;
+        P.r[b] = c + n2;
+        c = a256(c + reg);
+        const int nb = std::min(n, kDetBlock);
+        P.t[b] = c; c = a256(c + (n > kDetBlock ? (size_t)kDetBlock * n * 8 : 0));
+        P.dinv[b] = c; c = a256(c + (size_t)nb * nb * 8);
+        P.parts[b] = c; c = a256(c + (size_t)gemm_tiles(n, n) * 8);
+        P.rows[b] = c; c = a256(c + (size_t)n * 4);
+        P.cols[b] = c; c = a256(c + (size_t)n * 4);
+        P.bpiv[b] = c; c = a256(c + 2 * kDetBlock * 4);
+        P.nblocks[b] = (n + kDetBlock - 1) / kDetBlock;
+        P.blockres_start[b] = nbtot;
+        nbtot += P.nblocks[b];
+    }
+    P.off_blockres = c; c = a256(c + (size_t)nbtot * sizeof(gj_result));
+    P.off_ctl = c; c = a256(c + (size_t)batch * refine_ctl_bytes());
+    P.off_mem = c; c = a256(c + (size_t)batch * refine_member_bytes());
+    // FP64 fallback tables
+    P.fb.mats.resize(batch);
+    P.fb.off_mats = c; c = a256(c + sizeof(MatDesc) * batch);
+    P.fb.off_tasks = c; c = a256(c + sizeof(OnchipTask) * std::max<size_t>(1, P.e32.tasks.size()));
+    if (!P.e32.big_members.empty()) {
+        P.fb_nt = big_threads(P.e32.big_max_n, false);
+        P.off_fb_descs = c; c = a256(c + sizeof(BigDesc) * P.e32.big_members.size());
+        size_t nb = 0;
+        for (int m : P.e32.big_members) {
+            BigShape s = big_shape(n_host[m], false, P.fb_nt);
+            P.fb_shapes.push_back(s);
+            P.fb_bufs.push_back(big_bufs(s, false, P.region[m]));
+            nb += s.nblk;
+        }
+        P.off_fb_bmap = c; c = a256(c + sizeof(int2) * nb);
+        for (size_t x = 0; x < P.e32.big_members.size(); ++x)
+            for (int rb = 0; rb < P.fb_shapes[x].nblk; ++rb) P.fb_bmap.push_back(make_int2((int)x, rb));
+        P.fb_grid.assign(P.e32.big_max_n, 0);
+        for (int k = 0; k < P.e32.big_max_n; ++k)
+            for (size_t x = 0; x < P.e32.big_members.size(); ++x)
+                if (P.fb_shapes[x].n > k) P.fb_grid[k] += P.fb_shapes[x].nblk;
+    }
+    // product lists (shapes only here; pointers filled at call time)
+    int maxn = 0;
+    for (int b = 0; b < batch; ++b) maxn = std::max(maxn, (int)n_host[b]);
+    const int nsteps = (maxn + kDetBlock - 1) / kDetBlock;
+    P.det_blocks.resize(nsteps);
+    P.det_t.resize(nsteps);
+    P.det_s.resize(nsteps);
+    auto list_bytes = [&](GemmList &L, int count_probs, int count_tiles) {
+        L.off_probs = c; c = a256(c + sizeof(GemmArgs) * std::max(1, count_probs));
+        L.off_tiles = c; c = a256(c + sizeof(int2) * std::max(1, count_tiles));
+    };
+    int tiles_all = 0;
+    for (int b = 0; b < batch; ++b) tiles_all += gemm_tiles(n_host[b], n_host[b]);
+    list_bytes(P.r0, batch, tiles_all);
+    for (int p = 0; p < 2; ++p) {
+        list_bytes(P.upd[p], batch, tiles_all);
+        list_bytes(P.res[p], batch, tiles_all);
+    }
+    for (int s = 0; s < nsteps; ++s) {
+        int nprob = 0, tt = 0, ts = 0, nmat = 0;
+        for (int b = 0; b < batch; ++b) {
+            const int n = n_host[b], kb = s * kDetBlock;
+            if (n <= kb) continue;
+            ++nmat;
+            const int nbk = std::min(kDetBlock, n - kb), mm = n - kb - nbk;
+            if (mm > 0) { ++nprob; tt += gemm_tiles(nbk, mm); ts += gemm_tiles(mm, mm); }
+        }
+        P.det_blocks[s].off_mats = c; c = a256(c + sizeof(MatDesc) * std::max(1, nmat));
+        P.det_blocks[s].off_tasks = c; c = a256(c + sizeof(OnchipTask) * std::max(1, nmat));
+        list_bytes(P.det_t[s], nprob, tt);
+        list_bytes(P.det_s[s], nprob, ts);
+    }
+    P.total = c;
+    return true;
+}
+
+gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *off_host,
+                              const double *A, double *X, const int64_t *piv_off_host,
+                              int32_t *ipiv, int32_t *jpiv, gj_result *res, const Opts &o,
+                              char *w, size_t ws_bytes, hipStream_t s) {
+    RefBatchPlan P;
+    if (!plan_refined_batch(batch, n_host, P)) return GJ_E_INVALID_ARG;
+    if (ws_bytes < P.total) return GJ_E_WORKSPACE;
+    BatchPlan &E = P.e32;
+    double *wd = reinterpret_cast<double *>(w);
+    char *ctl = w + P.off_ctl;
+    gj_result *blockres = reinterpret_cast<gj_result *>(w + P.off_blockres);
+    const size_t cb = refine_ctl_bytes();
+
+    // ---- host copies of every device table
+    E.mats.resize(batch);
+    for (int b = 0; b < batch; ++b)
+        E.mats[b] = MatDesc{off_host[b], off_host[b], piv_off_host[b], n_host[b], n_host[b], n_host[b], b, nullptr};
+    std::vector<BigDesc> d32, d64;
+    for (size_t x = 0; x < E.big_members.size(); ++x) {
+        const int m = E.big_members[x];
+        d32.push_back(make_desc(E.big_shapes[x], E.big_bufs[x], w, A + off_host[m], n_host[m],
+                                X + off_host[m], n_host[m], ipiv + piv_off_host[m],
+                                jpiv + piv_off_host[m], res + m));
+        BigDesc d = make_desc(P.fb_shapes[x], P.fb_bufs[x], w, A + off_host[m], n_host[m],
+                              X + off_host[m], n_host[m], ipiv + piv_off_host[m],
+                              jpiv + piv_off_host[m], res + m);
+        d.run = ctl_run_fallback(ctl + (size_t)m * cb);
+        d64.push_back(d);
+    }
+    std::vector<int> big_index(batch, -1);
+    for (size_t x = 0; x < E.big_members.size(); ++x) big_index[E.big_members[x]] = (int)x;
+    // control records (pointers only; the state is reset on the device)
+    std::vector<char> ctl_host((size_t)batch * cb, 0);
+    std::vector<RefMember> mem(batch);
+    for (int b = 0; b < batch; ++b) {
+        const int n = n_host[b];
+        RefineCtl h;
+        std::memset(&h, 0, sizeof(h));
+        h.nparts = gemm_tiles(n, n);
+        h.partials = reinterpret_cast<double *>(w + P.parts[b]);
+        h.res = res + b;
+        std::memcpy(ctl_host.data() + (size_t)b * cb, &h, sizeof(h));
+        RefMember &m = mem[b];
+        std::memset(&m, 0, sizeof(m));
+        m.A = A + off_host[b]; m.lda = n; m.X = X + off_host[b]; m.ldx = n;
+        m.Xw = reinterpret_cast<double *>(w + P.xw[b]);
+        m.B = reinterpret_cast<double *>(w + P.r[b]);
+        m.ipiv = ipiv + piv_off_host[b]; m.jpiv = jpiv + piv_off_host[b];
+        if (big_index[b] >= 0) {
+            m.rows = d32[big_index[b]].rowphys; m.cols = d32[big_index[b]].colphys;
+        } else {
+            m.rows_buf = reinterpret_cast<int32_t *>(w + P.rows[b]);
+            m.cols_buf = reinterpret_cast<int32_t *>(w + P.cols[b]);
+            m.rows = m.rows_buf; m.cols = m.cols_buf;
+        }
+        m.blockres = blockres + P.blockres_start[b];
+        m.n = n; m.nblocks = P.nblocks[b];
+        P.fb.mats[b] = E.mats[b];
+        P.fb.mats[b].run = ctl_run_fallback(ctl + (size_t)b * cb);
+    }
+    // Newton-Schulz lists
+    for (int b = 0; b < batch; ++b) {
+        const int n = n_host[b];
+        const void *cm = ctl + (size_t)b * cb;
+        double *Xb = X + off_host[b], *Xwb = reinterpret_cast<double *>(w + P.xw[b]);
+        double *Rb = reinterpret_cast<double *>(w + P.r[b]);
+        double *pb = reinterpret_cast<double *>(w + P.parts[b]);
+        GemmArgs g;
+        std::memset(&g, 0, sizeof(g));
+        g.M = g.N = g.K = n;
+        g.A = A + off_host[b]; g.lda = n; g.B = Xb; g.ldb = n; g.D = Rb; g.ldd = n;
+        g.alpha = -1.0; g.gamma = 1.0; g.norm_partials = pb; g.run_flag = ctl_run_ns(cm);
+        P.r0.add(g);
+        for (int p = 0; p < 2; ++p) {   // p = iteration parity: odd reads X, writes Xw
+            double *Xs = p ? Xb : Xwb, *Xd = p ? Xwb : Xb;
+            GemmArgs u;
+            std::memset(&u, 0, sizeof(u));
+            u.M = u.N = u.K = n;
+            u.A = Xs; u.lda = n; u.B = Rb; u.ldb = n; u.C = Xs; u.ldc = n; u.D = Xd; u.ldd = n;
+            u.alpha = 1.0; u.beta = 1.0; u.run_flag = ctl_run_ns(cm);
+            P.upd[p].add(u);
+            GemmArgs r2 = g;
+            r2.B = Xd;
+            P.res[p].add(r2);
+        }
+    }
+    // determinant block steps
+    for (size_t st = 0; st < P.det_blocks.size(); ++st) {
+        OnchipSet &S = P.det_blocks[st];
+        S.mats.clear();
+        const int kb = (int)st * kDetBlock;
+        for (int b = 0; b < batch; ++b) {
+            const int n = n_host[b];
+            if (n <= kb) continue;
+            const void *cm = ctl + (size_t)b * cb;
+            const int nbk = std::min(kDetBlock, n - kb), mm = n - kb - nbk;
+            const int ldd = std::min(n, kDetBlock);
+            MatDesc md;
+            md.a_off = (int64_t)(P.r[b] / 8) + (int64_t)kb * n + kb;
+            md.x_off = (int64_t)(P.dinv[b] / 8);
+            md.piv_off = (int64_t)(P.bpiv[b] / 4);
+            md.n = nbk; md.lda = n; md.ldx = ldd;
+            md.res_idx = P.blockres_start[b] + (int)st;
+            md.run = ctl_run_det(cm);
+            S.mats.push_back(md);
+            if (mm > 0) {
+                double *Bb = reinterpret_cast<double *>(w + P.r[b]);
+                double *Tb = reinterpret_cast<double *>(w + P.t[b]);
+                GemmArgs g1;
+                std::memset(&g1, 0, sizeof(g1));
+                g1.M = nbk; g1.N = mm; g1.K = nbk;
+                g1.A = reinterpret_cast<double *>(w + P.dinv[b]); g1.lda = ldd;
+                g1.B = Bb + (int64_t)kb * n + kb + nbk; g1.ldb = n;
+                g1.D = Tb; g1.ldd = n;
+                g1.alpha = 1.0; g1.run_flag = ctl_run_det(cm);
+                P.det_t[st].add(g1);
+                GemmArgs g2;
+                std::memset(&g2, 0, sizeof(g2));
+                g2.M = mm; g2.N = mm; g2.K = nbk;
+                g2.A = Bb + (int64_t)(kb + nbk) * n + kb; g2.lda = n;
+                g2.B = Tb; g2.ldb = n;
+                g2.C = Bb + (int64_t)(kb + nbk) * n + kb + nbk; g2.ldc = n;
+                g2.D = const_cast<double *>(g2.C); g2.ldd = n;
+                g2.alpha = -1.0; g2.beta = 1.0; g2.run_flag = ctl_run_det(cm);
+                P.det_s[st].add(g2);
+            }
+        }
+        S.build();
+    }
+
+    // ---- upload (host tables die with this call: synchronise once)
+    if (!(o.flags & GJ_FLAG_REUSE_PLAN)) {
+        std::vector<std::pair<size_t, std::pair<const void *, size_t>>> up;
+        auto put = [&](size_t off, const void *p, size_t bytes) { if (bytes) up.push_back({off, {p, bytes}}); };
+        put(E.off_mats, E.mats.data(), sizeof(MatDesc) * batch);
+        put(E.off_tasks, E.tasks.data(), sizeof(OnchipTask) * E.tasks.size());
+        put(E.off_descs, d32.data(), sizeof(BigDesc) * d32.size());
+        put(E.off_bmap, E.bmap.data(), sizeof(int2) * E.bmap.size());
+        put(P.off_ctl, ctl_host.data(), ctl_host.size());
+        put(P.off_mem, mem.data(), sizeof(RefMember) * batch);
+        put(P.fb.off_mats, P.fb.mats.data(), sizeof(MatDesc) * batch);
+        put(P.fb.off_tasks, E.tasks.data(), sizeof(OnchipTask) * E.tasks.size());
+        put(P.off_fb_descs, d64.data(), sizeof(BigDesc) * d64.size());
+        put(P.off_fb_bmap, P.fb_bmap.data(), sizeof(int2) * P.fb_bmap.size());
+        auto put_list = [&](GemmList &L) {
+            put(L.off_probs, L.probs.data(), sizeof(GemmArgs) * L.probs.size());
+            put(L.off_tiles, L.tiles.data(), sizeof(int2) * L.tiles.size());
+        };
+        put_list(P.r0);
+        for (int p = 0; p < 2; ++p) { put_list(P.upd[p]); put_list(P.res[p]); }
+        for (size_t st = 0; st < P.det_blocks.size(); ++st) {
+            put(P.det_blocks[st].off_mats, P.det_blocks[st].mats.data(), sizeof(MatDesc) * P.det_blocks[st].mats.size());
+            put(P.det_blocks[st].off_tasks, P.det_blocks[st].tasks.data(), sizeof(OnchipTask) * P.det_blocks[st].tasks.size());
+            put_list(P.det_t[st]);
+            put_list(P.det_s[st]);
+        }
+        for (auto &u : up)
+            GJ_TRY(hipMemcpyAsync(w + u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, s));
+        GJ_TRY(hipStreamSynchronize(s));
+    }
+    uint32_t *queues = reinterpret_cast<uint32_t *>(w + E.off_queue);
+    auto run_onchip_set = [&](bool fp32, const MatDesc *mats, const OnchipTask *tasks,
+                              const int *cstart, const int *ccount, const double *Ab, double *Xb,
+                              int32_t *ip, int32_t *jp, gj_result *rs, double tol, double eps) -> gj_status {
+        GJ_TRY(launch_zero_u32(queues, kOnchipClasses, s));
+        for (int c = 0; c < kOnchipClasses; ++c) {
+            if (!ccount[c]) continue;
+            GJ_TRY(launch_onchip_class(fp32, c, mats, tasks + cstart[c], ccount[c], queues + c, MatDesc(),
+                                       Ab, Xb, ip, jp, rs, tol, eps, 0, nullptr, s));
+        }
+        return GJ_OK;
+    };
+    auto grouped = [&](GemmList &L) -> gj_status {
+        GJ_TRY(launch_gemm_f64_grouped(reinterpret_cast<const GemmArgs *>(w + L.off_probs),
+                                       reinterpret_cast<const int2 *>(w + L.off_tiles),
+                                       (int)L.tiles.size(), s));
+        return GJ_OK;
+    };
+    gj_status st;
+
+    // 1. FP32 elimination of every member
+    if (!E.tasks.empty()) {
+        st = run_onchip_set(true, reinterpret_cast<const MatDesc *>(w + E.off_mats),
+                            reinterpret_cast<const OnchipTask *>(w + E.off_tasks), E.cls_start,
+                            E.cls_count, A, X, ipiv, jpiv, res, 0.0, 0.0);
+        if (st != GJ_OK) return st;
+    }
+    if (!E.big_members.empty()) {
+        const int nb = (int)E.bmap.size();
+        GJ_TRY(launch_big(true, E.big_nt, reinterpret_cast<const BigDesc *>(w + E.off_descs),
+                          reinterpret_cast<const int2 *>(w + E.off_bmap), BigDesc(),
+                          E.grid_per_step.data(), nb, nb, E.big_max_n, nb, 0.0, 0.0, 0, o.events,
+                          nullptr, s));
+    }
+    GJ_TRY(launch_refine_start(ctl, batch, s));
+    // 2. Newton-Schulz on grouped MFMA products
+    if ((st = grouped(P.r0)) != GJ_OK) return st;
+    GJ_TRY(launch_refine_resid0(ctl, batch, s));
+    for (int it = 1; it <= o.max_refine_iters; ++it) {
+        if ((st = grouped(P.upd[it & 1])) != GJ_OK) return st;
+        if ((st = grouped(P.res[it & 1])) != GJ_OK) return st;
+        GJ_TRY(launch_refine_after_update(ctl, batch, it, o.max_refine_iters, kStall, s));
+    }
+    GJ_TRY(launch_refine_finish(ctl, batch, kAcceptResid, 1, s));
+    GJ_TRY(launch_copy_back(reinterpret_cast<const RefMember *>(w + P.off_mem), RefMember(), ctl,
+                            batch, 4, s));
+    // 3. FP64 elimination for the members whose refinement failed
+    if (!E.tasks.empty()) {
+        st = run_onchip_set(false, reinterpret_cast<const MatDesc *>(w + P.fb.off_mats),
+                            reinterpret_cast<const OnchipTask *>(w + P.fb.off_tasks), E.cls_start,
+                            E.cls_count, A, X, ipiv, jpiv, res, o.zero_tol, kEps64);
+        if (st != GJ_OK) return st;
+    }
+    if (!E.big_members.empty()) {
+        const int nb = (int)P.fb_bmap.size();
+        GJ_TRY(launch_big(false, P.fb_nt, reinterpret_cast<const BigDesc *>(w + P.off_fb_descs),
+                          reinterpret_cast<const int2 *>(w + P.off_fb_bmap), BigDesc(),
+                          P.fb_grid.data(), nb, nb, E.big_max_n, nb, o.zero_tol, kEps64, 0, nullptr,
+                          nullptr, s));
+    }
+    GJ_TRY(launch_fallback_mark(ctl, batch, s));
+    // 4. FP64 determinants: permuted copies, block elimination in lock step
+    const RefMember *memd = reinterpret_cast<const RefMember *>(w + P.off_mem);
+    GJ_TRY(launch_perms_from_pivots(memd, RefMember(), ctl, batch, s));
+    GJ_TRY(launch_gather_perm(memd, RefMember(), ctl, batch, 4, s));
+    for (size_t sb = 0; sb < P.det_blocks.size(); ++sb) {
+        OnchipSet &S = P.det_blocks[sb];
+        st = run_onchip_set(false, reinterpret_cast<const MatDesc *>(w + S.off_mats),
+                            reinterpret_cast<const OnchipTask *>(w + S.off_tasks), S.cls_start,
+                            S.cls_count, wd, wd, reinterpret_cast<int32_t *>(w),
+                            reinterpret_cast<int32_t *>(w) + kDetBlock, blockres, -1.0, kEps64);
+        if (st != GJ_OK) return st;
+        if ((st = grouped(P.det_t[sb])) != GJ_OK) return st;
+        if ((st = grouped(P.det_s[sb])) != GJ_OK) return st;
+    }
+    GJ_TRY(launch_det_combine(memd, RefMember(), ctl, batch, s));
+    GJ_TRY(launch_refine_iters(ctl, batch, s));
     return GJ_OK;
 }
 
@@ -561,8 +965,13 @@ size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
     }
     if (op == GJ_OP_INVERT_BATCHED) {
         if (n_or_batch < 1 || !n_host) return 0;
+        if (o.precision == GJ_PREC_FP32_REFINED) {
+            RefBatchPlan R;
+            if (!plan_refined_batch(n_or_batch, n_host, R)) return 0;
+            return R.total;
+        }
         BatchPlan P;
-        if (!plan_batch(n_or_batch, n_host, o.precision == GJ_PREC_FP32_REFINED, P)) return 0;
+        if (!plan_batch(n_or_batch, n_host, false, P)) return 0;
         return P.total;
     }
     return 0;
@@ -634,8 +1043,13 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         if (batch < 1 || !n_host || !off_host || !piv_off_host || !A || !X || !ipiv || !jpiv ||
             !res)
             return GJ_E_INVALID_ARG;
-        if (o.precision != GJ_PREC_FP64) return GJ_E_UNSUPPORTED;
         if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
+        for (int b = 0; b < batch; ++b)
+            if (n_host[b] < 1 || n_host[b] > kMaxN || off_host[b] < 0 || piv_off_host[b] < 0)
+                return GJ_E_INVALID_ARG;
+        if (o.precision == GJ_PREC_FP32_REFINED)
+            return run_refined_batched(batch, n_host, off_host, A, X, piv_off_host, ipiv, jpiv, res,
+                                       o, (char *)ws, ws_bytes, (hipStream_t)stream);
         const bool fp32 = false;
         BatchPlan P;
         if (!plan_batch(batch, n_host, fp32, P)) return GJ_E_INVALID_ARG;
@@ -655,6 +1069,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
             m.lda = n_host[b];
             m.ldx = n_host[b];
             m.res_idx = b;
+            m.run = nullptr;
         }
         std::vector<BigDesc> descs;
         for (size_t x = 0; x < P.big_members.size(); ++x) {

@@ -82,6 +82,7 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     using V = VecOf<T>;
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
+    if (d.run && *d.run == 0) return;
     const int rb = bm.y, t = threadIdx.x, n = d.n;
     const int tpr = d.tpr, rsub = t / tpr, tc = t % tpr, rg = NT / tpr;
     T *W = reinterpret_cast<T *>(d.W);
@@ -140,6 +141,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
+    if (d.run && *d.run == 0) return;
     const int n = d.n;
     if (k >= n) return;
     if (d.hdr->status != 0) return;
@@ -312,6 +314,7 @@ gj_big_finish(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
     if (run_flag && *run_flag == 0) return;
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
+    if (d.run && *d.run == 0) return;
     const int n = d.n, t = threadIdx.x;
     const int status = d.hdr->status;
     const int rank = (status == 0) ? n : d.hdr->rank;
@@ -359,6 +362,7 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
     if (run_flag && *run_flag == 0) return;
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
+    if (d.run && *d.run == 0) return;
     const int n = d.n, t = threadIdx.x;
     const int status = d.hdr->status;
     const T *W = reinterpret_cast<const T *>(d.W);

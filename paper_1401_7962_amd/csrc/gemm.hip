@@ -32,18 +32,14 @@ constexpr int LDB_S = BN + 2;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(NTH)
-gemm_f64_kernel(const GemmArgs g) {
-    if (g.run_flag && *g.run_flag == 0) return;
+// One 128 x 128 tile of D.  `b` is the tile index within the problem,
+// `part` the slot of its norm partial.
+__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
     __shared__ double As[BK][LDA_S];  // As[k][m]
     __shared__ double Bs[BK][LDB_S];  // Bs[k][n]
     __shared__ double s_red[NTH / kWave];
 
-    const int tiles_m = (g.M + BM - 1) / BM, tiles_n = (g.N + BN - 1) / BN;
-    const int ntiles = tiles_m * tiles_n;
-    // XCD-aware renumbering: hardware workgroup b runs on XCD b % 8
-    int b = blockIdx.x;
-    if (ntiles % 8 == 0) b = (b % 8) * (ntiles / 8) + b / 8;
+    const int tiles_n = (g.N + BN - 1) / BN;
     const int tm = b / tiles_n, tn = b % tiles_n;
     const int m0 = tm * BM, n0 = tn * BN;
 
@@ -135,13 +131,39 @@ gemm_f64_kernel(const GemmArgs g) {
         for (int off = 32; off >= 1; off >>= 1) ssq += __shfl_xor(ssq, off, kWave);
         if (lane == 0) s_red[w] = ssq;
         __syncthreads();
-        if (t == 0) g.norm_partials[blockIdx.x] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+        if (t == 0) g.norm_partials[part] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
     }
+}
+
+__global__ void __launch_bounds__(NTH)
+gemm_f64_kernel(const GemmArgs g) {
+    if (g.run_flag && *g.run_flag == 0) return;
+    const int ntiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    // XCD-aware renumbering: hardware workgroup b runs on XCD b % 8
+    int b = blockIdx.x;
+    if (ntiles % 8 == 0) b = (b % 8) * (ntiles / 8) + b / 8;
+    gemm_tile(g, b, blockIdx.x);
+}
+
+// Many independent products in one launch: workgroup -> (problem, tile).
+__global__ void __launch_bounds__(NTH)
+gemm_f64_grouped_kernel(const GemmArgs *__restrict__ probs, const int2 *__restrict__ tilemap) {
+    const int2 pt = tilemap[blockIdx.x];
+    const GemmArgs g = probs[pt.x];
+    if (g.run_flag && *g.run_flag == 0) return;
+    gemm_tile(g, pt.y, pt.y);
 }
 
 }  // namespace
 
 int gemm_tiles(int M, int N) { return ((M + BM - 1) / BM) * ((N + BN - 1) / BN); }
+
+hipError_t launch_gemm_f64_grouped(const GemmArgs *probs, const int2 *tilemap, int ntiles,
+                                   hipStream_t s) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_f64_grouped_kernel, dim3(ntiles), dim3(NTH), 0, s, probs, tilemap);
+    return hipGetLastError();
+}
 
 hipError_t launch_gemm_f64(const GemmArgs &g, hipStream_t s) {
     const int tiles = gemm_tiles(g.M, g.N);

@@ -224,6 +224,7 @@ struct MatDesc {
     int32_t lda;
     int32_t ldx;
     int32_t res_idx;
+    const int32_t *run;  // null, or a per-matrix flag: skip the matrix when 0
 };
 
 // On-chip task: kind 0 = one matrix on the whole 256-thread workgroup;
@@ -269,6 +270,7 @@ struct BigDesc {
     int32_t *ipiv, *jpiv;
     gj_result *res;
     int64_t mstride;      // stride between the two parities of a map (= ldw)
+    const int32_t *run;   // null, or a per-matrix flag: every kernel skips it when 0
     int32_t n, R, nblk, tpr;  // order, rows per workgroup, workgroups, threads per row
 };
 

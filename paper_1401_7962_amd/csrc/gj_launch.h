@@ -46,29 +46,67 @@ struct GemmArgs {
 };
 int gemm_tiles(int M, int N);
 hipError_t launch_gemm_f64(const GemmArgs &g, hipStream_t s);
+// grouped: workgroup b computes tile tilemap[b].y of problem probs[tilemap[b].x]
+// (norm partial slot = tile index within the problem)
+hipError_t launch_gemm_f64_grouped(const GemmArgs *probs, const int2 *tilemap, int ntiles,
+                                   hipStream_t s);
 
 // refinement path (refine.hip)
+// Per-matrix refinement state (device).  A single call has one; a batch has
+// one per member, all driven by the same launches.
+struct RefineCtl {
+    int32_t run_ns;        // refinement still running
+    int32_t run_fallback;  // plain FP64 elimination needed
+    int32_t run_det;       // FP64 block determinant needed
+    int32_t updates;       // Newton-Schulz updates kept
+    int32_t final_buf;     // 0: iterate in X, 1: iterate in the workspace copy
+    int32_t copy_back;     // 1: copy the workspace iterate into X
+    int32_t always;        // constant 1 (a run flag that is always set)
+    int32_t nparts;        // GEMM norm partials of this matrix
+    double r;              // ||R||_F of the kept iterate
+    double r0;             // ||R_0||_F
+    double *partials;
+    gj_result *res;
+};
+
+// Per-matrix buffers of the refined path (device pointers).
+struct RefMember {
+    const double *A;
+    int64_t lda;
+    double *X;
+    int64_t ldx;
+    double *Xw;                  // second iterate (ld n)
+    double *B;                   // permuted copy for the determinant (ld n)
+    int32_t *ipiv, *jpiv;
+    const int32_t *rows, *cols;  // FP32 pivot order as permutations
+    int32_t *rows_buf, *cols_buf;  // non-null: fill rows/cols by replaying the swaps
+    gj_result *blockres;         // one record per diagonal block
+    int32_t n, nblocks;
+};
 size_t refine_ctl_bytes();
+size_t refine_member_bytes();
 const int32_t *ctl_run_ns(const void *c);
 const int32_t *ctl_run_fallback(const void *c);
 const int32_t *ctl_run_det(const void *c);
 const int32_t *ctl_copy_back(const void *c);
 const int32_t *ctl_always(const void *c);
-hipError_t launch_refine_start(const gj_result *res32, void *ctl, hipStream_t s);
-hipError_t launch_refine_resid0(const double *partials, int np, void *ctl, hipStream_t s);
-hipError_t launch_refine_after_update(const double *partials, int np, void *ctl, int it,
-                                      int max_iters, double stall, hipStream_t s);
-hipError_t launch_refine_finish(void *ctl, double accept, int det_wanted, hipStream_t s);
-hipError_t launch_copy_flagged(const double *src, int64_t lds, double *dst, int64_t ldd, int n,
-                               const int32_t *flag, hipStream_t s);
-hipError_t launch_fallback_mark(gj_result *res, const void *ctl, hipStream_t s);
-hipError_t launch_perms_from_pivots(const int32_t *ipiv, const int32_t *jpiv, int n, int32_t *rows,
-                                    int32_t *cols, const int32_t *flag, hipStream_t s);
-hipError_t launch_gather_perm(const double *A, int64_t lda, const int32_t *rows, const int32_t *cols,
-                              int n, double *B, int64_t ldb, const int32_t *flag, hipStream_t s);
-hipError_t launch_det_combine(const gj_result *blocks, int nblocks, const int32_t *ipiv,
-                              const int32_t *jpiv, int n, gj_result *res, void *ctl, hipStream_t s);
-hipError_t launch_refine_iters(gj_result *res, const void *ctl, hipStream_t s);
+void *ctl_at(void *c, int m);
+hipError_t launch_refine_bind(void *ctl, gj_result *res, double *partials, int nparts, hipStream_t s);
+hipError_t launch_refine_start(void *ctls, int count, hipStream_t s);
+hipError_t launch_refine_resid0(void *ctls, int count, hipStream_t s);
+hipError_t launch_refine_after_update(void *ctls, int count, int it, int max_iters, double stall,
+                                      hipStream_t s);
+hipError_t launch_refine_finish(void *ctls, int count, double accept, int det_wanted, hipStream_t s);
+hipError_t launch_copy_back(const RefMember *mem, const RefMember &single, void *ctls, int count,
+                            int row_blocks, hipStream_t s);
+hipError_t launch_fallback_mark(void *ctls, int count, hipStream_t s);
+hipError_t launch_perms_from_pivots(const RefMember *mem, const RefMember &single, void *ctls,
+                                    int count, hipStream_t s);
+hipError_t launch_gather_perm(const RefMember *mem, const RefMember &single, void *ctls, int count,
+                              int row_blocks, hipStream_t s);
+hipError_t launch_det_combine(const RefMember *mem, const RefMember &single, void *ctls, int count,
+                              hipStream_t s);
+hipError_t launch_refine_iters(void *ctls, int count, hipStream_t s);
 int sumsq_blocks(int n);
 hipError_t launch_sumsq(const double *M, int64_t ld, int n, double *partials, hipStream_t s);
 hipError_t launch_resid(const double *pr, int nr, const double *pa, int na, const double *px, int nx,

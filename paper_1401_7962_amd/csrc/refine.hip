@@ -20,19 +20,6 @@
 
 namespace gj {
 
-struct RefineCtl {
-    int32_t run_ns;        // refinement still running
-    int32_t run_fallback;  // plain FP64 elimination needed
-    int32_t run_det;       // FP64 block determinant needed
-    int32_t updates;       // Newton-Schulz updates kept
-    int32_t final_buf;     // 0: iterate in X, 1: iterate in the workspace copy
-    int32_t copy_back;     // 1: copy the workspace iterate into X
-    int32_t always;        // constant 1 (a run flag that is always set)
-    int32_t pad;
-    double r;              // ||R||_F of the kept iterate
-    double r0;             // ||R_0||_F
-};
-
 namespace {
 
 __device__ double block_sum_fixed(const double *p, int np) {
@@ -47,12 +34,23 @@ __device__ double block_sum_fixed(const double *p, int np) {
         if (t < w) s[t] += s[t + w];
         __syncthreads();
     }
-    return s[0];
+    const double v = s[0];
+    __syncthreads();
+    return v;
 }
 
-__global__ void refine_start_kernel(const gj_result *res32, RefineCtl *ctl) {
+__global__ void refine_bind_kernel(RefineCtl *ctl, gj_result *res, double *partials, int nparts) {
     if (threadIdx.x != 0) return;
-    const bool ok = res32->code == GJ_RES_OK;
+    ctl->res = res;
+    ctl->partials = partials;
+    ctl->nparts = nparts;
+}
+
+__global__ void refine_start_kernel(RefineCtl *ctls, int count) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count) return;
+    RefineCtl *ctl = ctls + m;
+    const bool ok = ctl->res->code == GJ_RES_OK;
     ctl->run_ns = ok ? 1 : 0;
     ctl->run_fallback = ok ? 0 : 1;
     ctl->run_det = 0;
@@ -65,9 +63,10 @@ __global__ void refine_start_kernel(const gj_result *res32, RefineCtl *ctl) {
 }
 
 __global__ void __launch_bounds__(256)
-refine_resid0_kernel(const double *partials, int np, RefineCtl *ctl) {
+refine_resid0_kernel(RefineCtl *ctls) {
+    RefineCtl *ctl = ctls + blockIdx.x;
     if (!ctl->run_ns) return;
-    const double r = sqrt(block_sum_fixed(partials, np));
+    const double r = sqrt(block_sum_fixed(ctl->partials, ctl->nparts));
     if (threadIdx.x == 0) {
         ctl->r0 = r;
         ctl->r = r;
@@ -77,10 +76,10 @@ refine_resid0_kernel(const double *partials, int np, RefineCtl *ctl) {
 }
 
 __global__ void __launch_bounds__(256)
-refine_after_update_kernel(const double *partials, int np, RefineCtl *ctl, int it, int max_iters,
-                           double stall) {
+refine_after_update_kernel(RefineCtl *ctls, int it, int max_iters, double stall) {
+    RefineCtl *ctl = ctls + blockIdx.x;
     if (!ctl->run_ns) return;
-    const double rn = sqrt(block_sum_fixed(partials, np));
+    const double rn = sqrt(block_sum_fixed(ctl->partials, ctl->nparts));
     if (threadIdx.x != 0) return;
     const double r = ctl->r;
     if (!(rn < r)) {                     // no progress (or NaN): keep the previous iterate
@@ -96,8 +95,10 @@ refine_after_update_kernel(const double *partials, int np, RefineCtl *ctl, int i
     if ((r < 1.0 && rn > stall * r) || it >= max_iters || rn == 0.0) ctl->run_ns = 0;
 }
 
-__global__ void refine_finish_kernel(RefineCtl *ctl, double accept, int det_wanted) {
-    if (threadIdx.x != 0) return;
+__global__ void refine_finish_kernel(RefineCtl *ctls, int count, double accept, int det_wanted) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count) return;
+    RefineCtl *ctl = ctls + m;
     ctl->run_ns = 0;
     if (!ctl->run_fallback) {
         if (!(ctl->r <= accept)) ctl->run_fallback = 1;
@@ -106,58 +107,74 @@ __global__ void refine_finish_kernel(RefineCtl *ctl, double accept, int det_want
     ctl->run_det = (!ctl->run_fallback && det_wanted) ? 1 : 0;
 }
 
+__device__ inline const RefMember &pick(const RefMember *mem, const RefMember &single) {
+    return mem ? mem[blockIdx.x] : single;
+}
+
 __global__ void __launch_bounds__(256)
-copy_flagged_kernel(const double *src, int64_t lds, double *dst, int64_t ldd, int n,
-                    const int32_t *flag) {
-    if (!*flag) return;
-    for (int i = blockIdx.x; i < n; i += gridDim.x)
-        for (int j = threadIdx.x; j < n; j += 256) dst[(int64_t)i * ldd + j] = src[(int64_t)i * lds + j];
+copy_back_kernel(const RefMember *mem, RefMember single, const RefineCtl *ctls) {
+    const RefMember &m = pick(mem, single);
+    if (!ctls[blockIdx.x].copy_back) return;
+    for (int i = blockIdx.y; i < m.n; i += gridDim.y)
+        for (int j = threadIdx.x; j < m.n; j += 256)
+            m.X[(int64_t)i * m.ldx + j] = m.Xw[(int64_t)i * m.n + j];
 }
 
 // After the fallback run: mark its outcome.
-__global__ void refine_fallback_mark_kernel(gj_result *res, const RefineCtl *ctl) {
-    if (threadIdx.x != 0 || !ctl->run_fallback) return;
-    if (res->code == GJ_RES_OK) res->code = GJ_RES_REFINE_FALLBACK;
-    res->refine_iters = ctl->updates;
+__global__ void refine_fallback_mark_kernel(RefineCtl *ctls, int count) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count) return;
+    const RefineCtl *ctl = ctls + m;
+    if (!ctl->run_fallback) return;
+    if (ctl->res->code == GJ_RES_OK) ctl->res->code = GJ_RES_REFINE_FALLBACK;
+    ctl->res->refine_iters = ctl->updates;
 }
 
 // Row / column order of the FP32 run as permutations: the pivoted matrix is
-// B(a, b) = A(rows[a], cols[b]).  The swaps are replayed in step order.
-__global__ void perms_from_pivots_kernel(const int32_t *ipiv, const int32_t *jpiv, int n,
-                                         int32_t *rows, int32_t *cols, const int32_t *flag) {
-    if (!*flag || threadIdx.x != 0) return;
-    for (int i = 0; i < n; ++i) { rows[i] = i; cols[i] = i; }
-    for (int k = 0; k < n; ++k) {
-        const int r = ipiv[k], c = jpiv[k];
+// B(a, b) = A(rows[a], cols[b]).  The swaps are replayed in step order (only
+// where the streaming run's maps are not available).
+__global__ void perms_from_pivots_kernel(const RefMember *mem, RefMember single,
+                                         const RefineCtl *ctls) {
+    const RefMember &m = pick(mem, single);
+    if (!ctls[blockIdx.x].run_det || !m.rows_buf || threadIdx.x != 0) return;
+    int32_t *rows = m.rows_buf, *cols = m.cols_buf;
+    for (int i = 0; i < m.n; ++i) { rows[i] = i; cols[i] = i; }
+    for (int k = 0; k < m.n; ++k) {
+        const int r = m.ipiv[k], c = m.jpiv[k];
         int t = rows[k]; rows[k] = rows[r]; rows[r] = t;
         t = cols[k]; cols[k] = cols[c]; cols[c] = t;
     }
 }
 
 __global__ void __launch_bounds__(256)
-gather_perm_kernel(const double *A, int64_t lda, const int32_t *rows, const int32_t *cols, int n,
-                   double *B, int64_t ldb, const int32_t *flag) {
-    if (!*flag) return;
-    for (int a = blockIdx.x; a < n; a += gridDim.x) {
-        const double *Ar = A + (int64_t)rows[a] * lda;
-        for (int b = threadIdx.x; b < n; b += 256) B[(int64_t)a * ldb + b] = Ar[cols[b]];
+gather_perm_kernel(const RefMember *mem, RefMember single, const RefineCtl *ctls) {
+    const RefMember &m = pick(mem, single);
+    if (!ctls[blockIdx.x].run_det) return;
+    for (int a = blockIdx.y; a < m.n; a += gridDim.y) {
+        const double *Ar = m.A + (int64_t)m.rows[a] * m.lda;
+        for (int b = threadIdx.x; b < m.n; b += 256) m.B[(int64_t)a * m.n + b] = Ar[m.cols[b]];
     }
 }
 
 // det A = sign(P) sign(Q) prod det(S11) over the diagonal blocks.
-__global__ void det_combine_kernel(const gj_result *blocks, int nblocks, const int32_t *ipiv,
-                                   const int32_t *jpiv, int n, gj_result *res, RefineCtl *ctl) {
-    if (!ctl->run_det || threadIdx.x != 0) return;
+__global__ void det_combine_kernel(const RefMember *mem, RefMember single, RefineCtl *ctls,
+                                   int count) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count) return;
+    const RefMember &m = mem ? mem[idx] : single;
+    RefineCtl *ctl = ctls + idx;
+    if (!ctl->run_det) return;
+    gj_result *res = ctl->res;
     int sign = 1;
-    for (int k = 0; k < n; ++k) {
-        if (ipiv[k] != k) sign = -sign;
-        if (jpiv[k] != k) sign = -sign;
+    for (int k = 0; k < m.n; ++k) {
+        if (m.ipiv[k] != k) sign = -sign;
+        if (m.jpiv[k] != k) sign = -sign;
     }
     DetAcc<double> d;
     d.init();
     bool bad = false;
-    for (int b = 0; b < nblocks; ++b) {
-        const gj_result br = blocks[b];
+    for (int b = 0; b < m.nblocks; ++b) {
+        const gj_result br = m.blockres[b];
         if (br.code != GJ_RES_OK) { bad = true; break; }
         d.mul(br.det_mant);      // exact power-of-two rescaling: mantissa product only
         d.e += br.det_exp;
@@ -179,8 +196,10 @@ __global__ void det_combine_kernel(const gj_result *blocks, int nblocks, const i
     res->logabsdet = log(d.m) + (double)d.e * 0.69314718055994530942;
 }
 
-__global__ void refine_iters_kernel(gj_result *res, const RefineCtl *ctl) {
-    if (threadIdx.x == 0 && !ctl->run_fallback) res->refine_iters = ctl->updates;
+__global__ void refine_iters_kernel(RefineCtl *ctls, int count) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= count) return;
+    if (!ctls[m].run_fallback) ctls[m].res->refine_iters = ctls[m].updates;
 }
 
 // Per-workgroup sums of squares of an n x n matrix (for ||.||_F).
@@ -215,72 +234,81 @@ resid_kernel(const double *pr, int nr, const double *pa, int na, const double *p
 }  // namespace
 
 size_t refine_ctl_bytes() { return sizeof(RefineCtl); }
+size_t refine_member_bytes() { return sizeof(RefMember); }
 const int32_t *ctl_run_ns(const void *c) { return &((const RefineCtl *)c)->run_ns; }
 const int32_t *ctl_run_fallback(const void *c) { return &((const RefineCtl *)c)->run_fallback; }
 const int32_t *ctl_run_det(const void *c) { return &((const RefineCtl *)c)->run_det; }
 const int32_t *ctl_copy_back(const void *c) { return &((const RefineCtl *)c)->copy_back; }
 const int32_t *ctl_always(const void *c) { return &((const RefineCtl *)c)->always; }
+void *ctl_at(void *c, int m) { return (RefineCtl *)c + m; }
 
 #define GJ_CHECK_LAUNCH() do { hipError_t e_ = hipGetLastError(); if (e_ != hipSuccess) return e_; } while (0)
+static inline int g256(int count) { return (count + 255) / 256; }
 
-hipError_t launch_refine_start(const gj_result *res32, void *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(refine_start_kernel, dim3(1), dim3(64), 0, s, res32, (RefineCtl *)ctl);
+hipError_t launch_refine_bind(void *ctl, gj_result *res, double *partials, int nparts, hipStream_t s) {
+    hipLaunchKernelGGL(refine_bind_kernel, dim3(1), dim3(64), 0, s, (RefineCtl *)ctl, res, partials, nparts);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_refine_resid0(const double *partials, int np, void *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(refine_resid0_kernel, dim3(1), dim3(256), 0, s, partials, np, (RefineCtl *)ctl);
+hipError_t launch_refine_start(void *ctls, int count, hipStream_t s) {
+    hipLaunchKernelGGL(refine_start_kernel, dim3(g256(count)), dim3(256), 0, s, (RefineCtl *)ctls, count);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_refine_after_update(const double *partials, int np, void *ctl, int it,
-                                      int max_iters, double stall, hipStream_t s) {
-    hipLaunchKernelGGL(refine_after_update_kernel, dim3(1), dim3(256), 0, s, partials, np,
-                       (RefineCtl *)ctl, it, max_iters, stall);
+hipError_t launch_refine_resid0(void *ctls, int count, hipStream_t s) {
+    hipLaunchKernelGGL(refine_resid0_kernel, dim3(count), dim3(256), 0, s, (RefineCtl *)ctls);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_refine_finish(void *ctl, double accept, int det_wanted, hipStream_t s) {
-    hipLaunchKernelGGL(refine_finish_kernel, dim3(1), dim3(64), 0, s, (RefineCtl *)ctl, accept,
-                       det_wanted);
+hipError_t launch_refine_after_update(void *ctls, int count, int it, int max_iters, double stall,
+                                      hipStream_t s) {
+    hipLaunchKernelGGL(refine_after_update_kernel, dim3(count), dim3(256), 0, s, (RefineCtl *)ctls,
+                       it, max_iters, stall);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_copy_flagged(const double *src, int64_t lds, double *dst, int64_t ldd, int n,
-                               const int32_t *flag, hipStream_t s) {
-    const int grid = n < 1024 ? n : 1024;
-    hipLaunchKernelGGL(copy_flagged_kernel, dim3(grid), dim3(256), 0, s, src, lds, dst, ldd, n, flag);
+hipError_t launch_refine_finish(void *ctls, int count, double accept, int det_wanted, hipStream_t s) {
+    hipLaunchKernelGGL(refine_finish_kernel, dim3(g256(count)), dim3(256), 0, s, (RefineCtl *)ctls,
+                       count, accept, det_wanted);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_fallback_mark(gj_result *res, const void *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(refine_fallback_mark_kernel, dim3(1), dim3(64), 0, s, res,
-                       (const RefineCtl *)ctl);
+hipError_t launch_copy_back(const RefMember *mem, const RefMember &single, void *ctls, int count,
+                            int row_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(copy_back_kernel, dim3(count, row_blocks), dim3(256), 0, s, mem, single,
+                       (const RefineCtl *)ctls);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_perms_from_pivots(const int32_t *ipiv, const int32_t *jpiv, int n, int32_t *rows,
-                                    int32_t *cols, const int32_t *flag, hipStream_t s) {
-    hipLaunchKernelGGL(perms_from_pivots_kernel, dim3(1), dim3(64), 0, s, ipiv, jpiv, n, rows, cols, flag);
+hipError_t launch_fallback_mark(void *ctls, int count, hipStream_t s) {
+    hipLaunchKernelGGL(refine_fallback_mark_kernel, dim3(g256(count)), dim3(256), 0, s,
+                       (RefineCtl *)ctls, count);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_gather_perm(const double *A, int64_t lda, const int32_t *rows, const int32_t *cols,
-                              int n, double *B, int64_t ldb, const int32_t *flag, hipStream_t s) {
-    const int grid = n < 2048 ? n : 2048;
-    hipLaunchKernelGGL(gather_perm_kernel, dim3(grid), dim3(256), 0, s, A, lda, rows, cols, n, B, ldb, flag);
+hipError_t launch_perms_from_pivots(const RefMember *mem, const RefMember &single, void *ctls,
+                                    int count, hipStream_t s) {
+    hipLaunchKernelGGL(perms_from_pivots_kernel, dim3(count), dim3(64), 0, s, mem, single,
+                       (const RefineCtl *)ctls);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_det_combine(const gj_result *blocks, int nblocks, const int32_t *ipiv,
-                              const int32_t *jpiv, int n, gj_result *res, void *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(det_combine_kernel, dim3(1), dim3(64), 0, s, blocks, nblocks, ipiv, jpiv, n,
-                       res, (RefineCtl *)ctl);
+hipError_t launch_gather_perm(const RefMember *mem, const RefMember &single, void *ctls, int count,
+                              int row_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(gather_perm_kernel, dim3(count, row_blocks), dim3(256), 0, s, mem, single,
+                       (const RefineCtl *)ctls);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }
-hipError_t launch_refine_iters(gj_result *res, const void *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(refine_iters_kernel, dim3(1), dim3(64), 0, s, res, (const RefineCtl *)ctl);
+hipError_t launch_det_combine(const RefMember *mem, const RefMember &single, void *ctls, int count,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(det_combine_kernel, dim3(g256(count)), dim3(256), 0, s, mem, single,
+                       (RefineCtl *)ctls, count);
+    GJ_CHECK_LAUNCH();
+    return hipSuccess;
+}
+hipError_t launch_refine_iters(void *ctls, int count, hipStream_t s) {
+    hipLaunchKernelGGL(refine_iters_kernel, dim3(g256(count)), dim3(256), 0, s, (RefineCtl *)ctls, count);
     GJ_CHECK_LAUNCH();
     return hipSuccess;
 }

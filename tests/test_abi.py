@@ -34,6 +34,12 @@ def test_header_lists_the_boundary():
         assert f in names
 
 
+def test_library_resolves_every_symbol_at_load():
+    """RTLD_NOW: an undefined symbol fails here, not at the first call."""
+    import torch  # noqa: F401  -- the HIP runtime the library binds to
+    ctypes.CDLL(gj.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
+
+
 def test_every_declared_symbol_is_exported(lib):
     out = subprocess.run(["nm", "-D", "--defined-only", gj.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout

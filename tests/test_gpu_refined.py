@@ -118,3 +118,60 @@ def test_want_resid(gj, n, prec):
     r = gj.results_to_dicts(res)[0]
     want = oracle.residual(A, X.cpu().numpy())
     assert abs(r["resid"] - want) <= 1e-2 * want + 1e-18
+
+
+def test_refined_batched_mixed(gj):
+    """A packed batch through the refined path: every on-chip class, the
+    streaming FP32 path, an exactly singular member and one whose entries
+    underflow FP32 (fallback), each against the same bars as a single call."""
+    import torch
+    rng = inputs.rng_for(0, 6400)
+    sizes = [1, 3, 7, 8, 12, 16, 20, 33, 40, 64, 65, 90, 128, 129, 150, 200, 256, 300]
+    conds = [10.0 ** rng.uniform(1, 8) for _ in sizes]
+    mats = [inputs.conditioned(n, c, rng) if n > 1 else np.array([[2.5]]) for n, c in zip(sizes, conds)]
+    H = inputs.sylvester_hadamard(64)
+    Hs = H.copy()
+    Hs[:, 63] = H[:, 0] + H[:, 1]
+    mats.append(Hs)
+    sizes.append(64)
+    conds.append(np.inf)
+    mats.append(rng.standard_normal((70, 70)) * 1e-50)
+    sizes.append(70)
+    conds.append(np.nan)
+    sizes = np.array(sizes, dtype=np.int32)
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes.astype(np.int64) ** 2)[:-1]
+    packed = np.concatenate([m.ravel() for m in mats])
+    opts = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED)
+    X, ipiv, jpiv, res, poff = gj.gj_invert_batched(sizes, offs, torch.from_numpy(packed).to("cuda"),
+                                                     opts=opts)
+    torch.cuda.synchronize()
+    Xh, ih, jh = X.cpu().numpy(), ipiv.cpu().numpy(), jpiv.cpu().numpy()
+    rs = gj.results_to_dicts(res)
+    for b, (n, A) in enumerate(zip(sizes, mats)):
+        n = int(n)
+        Xb = Xh[offs[b]:offs[b] + n * n].reshape(n, n)
+        ib, jb = ih[poff[b]:poff[b] + n], jh[poff[b]:poff[b] + n]
+        r = rs[b]
+        where = f"member {b} n={n} cond={conds[b]:.2g}"
+        if np.isinf(conds[b]):
+            assert r["code"] == 1 and r["rank"] == n - 1, where
+            continue
+        if np.isnan(conds[b]):
+            Xo, io, jo, ro = oracle.gj_invert_f64(A)
+            assert r["code"] == 3 and Xb.tobytes() == Xo.tobytes(), where
+            assert np.array_equal(ib, io) and np.array_equal(jb, jo), where
+            continue
+        assert r["code"] == 0, (where, r)
+        X32, i32, j32, _ = oracle.gj_invert_f32(A.astype(np.float32))
+        assert np.array_equal(ib, i32) and np.array_equal(jb, j32), where
+        Xo, _, _, _ = oracle.gj_invert_f64(A)
+        Xt, _, _, _ = oracle.gj_invert_f80(A)
+        if conds[b] <= 1e4:
+            assert _rel(Xb, Xo) <= 1e-12, where
+        assert _rel(Xb, Xt) <= 4 * _rel(Xo, Xt) + 1e-14, where
+        _, upd, _, _ = oracle.newton_schulz(A, X32.astype(np.float64))
+        assert abs(r["refine_iters"] - upd) <= 1, where
+        lu = oracle.lu_static_det_f64(A, i32, j32)
+        assert r["det_sign"] == lu["det_sign"], where
+        assert abs(r["logabsdet"] - lu["logabsdet"]) <= max(1e-12, n * conds[b] * 2.0 ** -53) * max(1.0, abs(lu["logabsdet"])), where
