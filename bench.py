@@ -157,6 +157,76 @@ def bench_latency_small(reps: int = 200):
     return out
 
 
+def _graph_time(call, reps):
+    """Capture call(stream) once in a HIP graph, replay it ``reps`` times
+    between events; returns the best milliseconds per replay."""
+    import torch
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            call(s)
+    torch.cuda.synchronize()
+    cur = torch.cuda.current_stream()
+    e = _events(2 * reps, cur)
+    for k in range(reps):
+        e[2 * k].record()
+        g.replay()
+        e[2 * k + 1].record()
+    torch.cuda.synchronize()
+    best = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+    del g
+    return best
+
+
+def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
+    """20,000 matrices, n log-uniform in [32,512], U diag(s) V^T with cond
+    log-uniform in [1e2,1e8]: FP32 elimination + FP64 Newton-Schulz +
+    FP64 determinant for every member, against the plain FP64 elimination
+    of the same batch; each timed as a replayed HIP graph."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    t0 = time.perf_counter()
+    sizes, offs, A, conds = inputs.batch_conditioned(batch, device="cuda")
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    poff = np.zeros(batch, dtype=np.int64)
+    poff[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
+    out = {"batch": batch, "input_generation_s": round(gen_s, 1)}
+    Xs = {}
+    for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
+        opts = gj.make_opts(precision=prec)
+        X = torch.empty_like(A)
+        ip = torch.empty(int(sizes.sum()), dtype=torch.int32, device="cuda")
+        jp = torch.empty_like(ip)
+        res = torch.empty(batch * gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        ws = torch.empty(gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, batch, sizes, opts),
+                         dtype=torch.uint8, device="cuda")
+        gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, opts, ws)   # uploads the plan
+        torch.cuda.synchronize()
+        reuse = gj.make_opts(precision=prec, flags=gj.GJ_FLAG_REUSE_PLAN)
+        ms = _graph_time(lambda st: gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, reuse,
+                                                          ws, st), reps)
+        del ws
+        raw = np.frombuffer(res.cpu().numpy().tobytes(), dtype=np.uint8).reshape(batch, gj.RESULT_BYTES)
+        codes = raw[:, 0:4].copy().view(np.int32)[:, 0]
+        iters = raw[:, 12:16].copy().view(np.int32)[:, 0]
+        logdet = raw[:, 40:48].copy().view(np.float64)[:, 0]
+        cf = sizes * np.log(conds) / 2.0
+        rel_det = np.abs(logdet - cf) / np.abs(cf)
+        out[name] = {"ms": round(ms, 2), "inversions_per_s": round(batch / (ms * 1e-3), 1),
+                     "codes": {str(c): int((codes == c).sum()) for c in np.unique(codes)},
+                     "mean_refine_iters": float(iters.mean()),
+                     "max_rel_logdet_err_vs_closed_form": float(rel_det.max())}
+        Xs[name] = X
+    d = torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"])
+    out["refined_vs_plain_rel_frobenius_whole_batch"] = float(d)
+    out["speedup_refined_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined"]["ms"], 3)
+    return out
+
+
 def bench_batch_uneven(batch: int = 100_000, reps: int = 3):
     """100,000 FP64 matrices, n uniform in [8,128], 1% rank n-1: one persistent
     on-chip launch.  Reports inversions/s and FP64 FMA throughput (n^3 FMAs =
@@ -178,14 +248,8 @@ def bench_batch_uneven(batch: int = 100_000, reps: int = 3):
     gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, None, ws)   # uploads the plan
     torch.cuda.synchronize()
     reuse = gj.make_opts(flags=gj.GJ_FLAG_REUSE_PLAN)
-    stream = torch.cuda.current_stream()
-    e = _events(2 * reps, stream)
-    for k in range(reps):
-        e[2 * k].record()
-        gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, reuse, ws)
-        e[2 * k + 1].record()
-    torch.cuda.synchronize()
-    ms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+    ms = _graph_time(lambda st: gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, reuse,
+                                                      ws, st), reps)
     codes = np.frombuffer(res.cpu().numpy().tobytes(), dtype=np.int32).reshape(batch, 14)[:, 0]
     flops = 2.0 * float((sizes.astype(np.float64) ** 3).sum())
     return {
@@ -348,6 +412,9 @@ def main():
         torch.cuda.empty_cache()
         extras["conditioned_8192"] = bench_conditioned_8192()
         print("bench: 8192 plain vs refined done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["batch_conditioned_20k"] = bench_batch_conditioned()
+        print("bench: 20k refined batch done", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["extras"] = extras
     if not args.no_cpu_baseline:

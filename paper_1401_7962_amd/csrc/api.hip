@@ -1,10 +1,15 @@
 // api.hip -- the C ABI of libgj (see include/gj.h): argument checks, path
 // selection, workspace layout and kernel launches.  No C++ exception leaves
 // this file.
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "gj_launch.h"
@@ -50,6 +55,47 @@ int env_int(const char *name, int dflt) {
     return std::atoi(v);
 }
 
+// ------------------------------------------------------------ tuning table
+// Written by the project's autotuner (paper_1401_7962_amd/tune.py) as lines
+//     big_rows <f32|f64> <n_min> <n_max> <rows per workgroup>
+// and read once from $GJ_TUNE_FILE, else from gj_tune.txt beside libgj.so.
+// $GJ_BIG_ROWS, when set, overrides it (the autotuner uses that to sweep).
+struct TuneEntry { int fp32, nmin, nmax, rows; };
+std::vector<TuneEntry> g_tune;
+std::once_flag g_tune_once;
+
+void load_tune_table() {
+    std::string path;
+    if (const char *f = std::getenv("GJ_TUNE_FILE")) {
+        path = f;
+    } else {
+        Dl_info info;
+        if (dladdr((void *)&load_tune_table, &info) && info.dli_fname) {
+            path = info.dli_fname;
+            const size_t slash = path.rfind('/');
+            path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/gj_tune.txt";
+        }
+    }
+    FILE *fp = path.empty() ? nullptr : std::fopen(path.c_str(), "r");
+    if (!fp) return;
+    char line[256];
+    while (std::fgets(line, sizeof(line), fp)) {
+        char key[64], prec[16];
+        int lo, hi, v;
+        if (std::sscanf(line, "%63s %15s %d %d %d", key, prec, &lo, &hi, &v) == 5 &&
+            std::strcmp(key, "big_rows") == 0 && v >= 1 && v <= 64 && lo <= hi)
+            g_tune.push_back(TuneEntry{std::strcmp(prec, "f32") == 0 ? 1 : 0, lo, hi, v});
+    }
+    std::fclose(fp);
+}
+
+int tuned_rows(bool fp32, int n) {
+    std::call_once(g_tune_once, load_tune_table);
+    for (const TuneEntry &e : g_tune)
+        if (e.fp32 == (fp32 ? 1 : 0) && n >= e.nmin && n <= e.nmax) return e.rows;
+    return 0;
+}
+
 // ------------------------------------------------------ streaming-path plan
 struct BigShape {
     int n, nt, tpr, R, nblk;
@@ -77,6 +123,7 @@ BigShape big_shape(int n, bool fp32, int nt) {
     s.tpr = tpr;
     const int rg = nt / tpr;
     int R = env_int("GJ_BIG_ROWS", 0);
+    if (R <= 0) R = tuned_rows(fp32, n);
     if (R <= 0) R = std::max(1, n / 512);
     R = std::max(R, rg);
     R = std::min(R, 64);

@@ -125,9 +125,16 @@ def single_conditioned(n: int = 8192, cond: float = 1e6, offset: int = 0, device
 
 
 def batch_conditioned(batch: int = 20_000, nmin: int = 32, nmax: int = 512,
-                      log10_cond: tuple = (2.0, 8.0), offset: int = 0):
+                      log10_cond: tuple = (2.0, 8.0), offset: int = 0, device=None):
     """Packed batch of U diag(s) V^T members.  Returns (sizes, offsets,
-    packed float64 buffer, conds)."""
+    packed buffer, conds).  Without ``device`` every member is built with
+    NumPy in index order (float64 array, det U = det V = +1).  With
+    ``device`` (a torch device) the members of each order are built together
+    there: Gaussian draws from torch's device generator seeded with the same
+    seed, orthonormalised by Cholesky QR applied twice (the Q of the QR with
+    positive diag(R), i.e. Haar), orders ascending; the determinant signs are
+    left as drawn (|det A| = prod s still holds), and the packed buffer is a
+    device tensor."""
     rng = rng_for(5, offset)
     u = rng.random(batch)
     sizes = np.rint(nmin * (nmax / nmin) ** u).astype(np.int32)
@@ -135,10 +142,39 @@ def batch_conditioned(batch: int = 20_000, nmin: int = 32, nmax: int = 512,
     sq = sizes.astype(np.int64) ** 2
     offs = np.zeros(batch, dtype=np.int64)
     offs[1:] = np.cumsum(sq)[:-1]
-    packed = np.empty(int(sq.sum()))
-    for b in range(batch):
-        n = int(sizes[b])
-        packed[offs[b]: offs[b] + n * n] = conditioned(n, float(conds[b]), rng).ravel()
+    if device is None:
+        packed = np.empty(int(sq.sum()))
+        for b in range(batch):
+            n = int(sizes[b])
+            packed[offs[b]: offs[b] + n * n] = conditioned(n, float(conds[b]), rng).ravel()
+        return sizes, offs, packed, conds
+    import torch
+    packed = torch.empty(int(sq.sum()), dtype=torch.float64, device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(SEED_BASE + 5 + offset)
+
+    def haar(count, n):
+        # Q of Z = QR with diag(R) > 0 (Haar), by Cholesky QR applied twice:
+        # R^T R = Z^T Z, Q = Z R^-1.  The determinant sign is left as drawn.
+        Q = torch.randn((count, n, n), generator=gen, dtype=torch.float64, device=device)
+        for _ in range(2):
+            G = torch.bmm(Q.transpose(1, 2).contiguous(), Q)
+            L = torch.linalg.cholesky(G)
+            Q = torch.linalg.solve_triangular(L, Q.transpose(1, 2).contiguous(),
+                                              upper=False).transpose(1, 2).contiguous()
+        return Q
+
+    for n in np.unique(sizes):
+        n = int(n)
+        idx = np.nonzero(sizes == n)[0]
+        U = haar(len(idx), n)
+        V = haar(len(idx), n)
+        s = torch.from_numpy(conds[idx][:, None] ** (np.arange(n) / max(n - 1, 1))[None, :]).to(device)
+        A = torch.bmm((U * s[:, None, :]).contiguous(), V.transpose(1, 2).contiguous())
+        flat = (torch.from_numpy(offs[idx]).to(device)[:, None]
+                + torch.arange(n * n, device=device)[None, :]).reshape(-1)
+        packed[flat] = A.reshape(-1)
+        del U, V, A, flat
     return sizes, offs, packed, conds
 
 
