@@ -195,6 +195,15 @@ def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
     poff = np.zeros(batch, dtype=np.int64)
     poff[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
     out = {"batch": batch, "input_generation_s": round(gen_s, 1)}
+    # independent determinant reference on the same bytes: torch's LU slogdet
+    lu_ref = np.empty(batch)
+    for n in np.unique(sizes):
+        n = int(n)
+        idx = np.nonzero(sizes == n)[0]
+        base = torch.from_numpy(offs[idx]).to(A.device)
+        M = A[(base[:, None] + torch.arange(n * n, device=A.device)[None, :])].reshape(len(idx), n, n)
+        lu_ref[idx] = torch.linalg.slogdet(M)[1].cpu().numpy()
+        del M, base
     Xs = {}
     for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
         opts = gj.make_opts(precision=prec)
@@ -219,7 +228,8 @@ def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
         out[name] = {"ms": round(ms, 2), "inversions_per_s": round(batch / (ms * 1e-3), 1),
                      "codes": {str(c): int((codes == c).sum()) for c in np.unique(codes)},
                      "mean_refine_iters": float(iters.mean()),
-                     "max_rel_logdet_err_vs_closed_form": float(rel_det.max())}
+                     "max_rel_logdet_err_vs_closed_form": float(rel_det.max()),
+                     "max_rel_logdet_err_vs_lu_slogdet": float((np.abs(logdet - lu_ref) / np.abs(lu_ref)).max())}
         Xs[name] = X
     d = torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"])
     out["refined_vs_plain_rel_frobenius_whole_batch"] = float(d)
@@ -338,6 +348,12 @@ def cpu_baseline(n: int = 4096, sample_steps: int = 256):
     }
 
 
+LEGS = {"latency_small": lambda: bench_latency_small(),
+        "batch_uneven_100k": lambda: bench_batch_uneven(),
+        "conditioned_8192": lambda: bench_conditioned_8192(),
+        "batch_conditioned_20k": lambda: bench_batch_conditioned()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,6 +366,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy, whose rocprofv3 FETCH_SIZE and "
                          "WRITE_SIZE calibrate the counters")
+    ap.add_argument("--leg", choices=sorted(LEGS),
+                    help="run one secondary workload alone and print its result (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -361,6 +379,9 @@ def main():
     import paper_1401_7962_amd as gj
     gj.load_library()
     torch.cuda.init()
+    if args.leg:
+        print(json.dumps({"leg": args.leg, **LEGS[args.leg]()}), flush=True)
+        return
 
     if args.copy_calibration:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")

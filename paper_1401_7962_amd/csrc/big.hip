@@ -32,12 +32,37 @@ template <typename T> struct VecOf;
 template <> struct VecOf<double> { static constexpr int V = 2; using type = double2; using itype = int2; };
 template <> struct VecOf<float> { static constexpr int V = 4; using type = float4; using itype = int4; };
 
+// Row traffic of the working array (one 16-byte vector per access).  With
+// NTL the loads are nontemporal: once the swept array is larger than the
+// Infinity Cache nothing read in a step is read again before it is evicted.
+template <typename VT> struct NVec;
+template <> struct NVec<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct NVec<float4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <bool NTL, typename VT> __device__ __forceinline__ VT row_ld(gptr<const VT> p) {
+    if constexpr (NTL) {
+        using NV = typename NVec<VT>::type;
+        const NV nv = __builtin_nontemporal_load(reinterpret_cast<gptr<const NV>>(p));
+        VT v;
+        __builtin_memcpy(&v, &nv, sizeof(NV));
+        return v;
+    } else {
+        return *p;
+    }
+}
+template <typename VT> __device__ __forceinline__ void row_st(gptr<VT> p, const VT &v) { *p = v; }
+
 template <typename VT, typename T>
 __device__ inline T vget(const VT &x, int e) { return reinterpret_cast<const T *>(&x)[e]; }
 template <typename VT, typename T>
 __device__ inline void vset(VT &x, int e, T v) { reinterpret_cast<T *>(&x)[e] = v; }
 
 constexpr int kNch = 8;  // column chunks per thread: n <= kNch * V * threads-per-row
+// Rows a thread holds in registers at once in the step kernel (their loads
+// are in flight together; the first group is requested before the candidate
+// reduction).  The 1024-thread workgroups have 128 VGPRs per lane: they load
+// each chunk where it is used.
+template <int NT> constexpr bool kEarlyRows = NT < 1024;
+template <int NT> constexpr int kRowGroup = kEarlyRows<NT> ? 2 : 1;
 
 // Workgroup-wide argmax of BigPart-like candidates, keyed on the logical
 // position.  Result broadcast to every thread.
@@ -123,7 +148,7 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 }
 
 // ------------------------------------------------------------------ step
-template <typename T, int NT>
+template <typename T, int NT, bool NTL>
 __global__ void __launch_bounds__(NT)
 gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
             int k, double zero_tol, double eps_default, int det_only,
@@ -141,35 +166,64 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
-    if (d.run && *d.run == 0) return;
     const int n = d.n;
     if (k >= n) return;
-    if (d.hdr->status != 0) return;
+    if (d.run && *glb(d.run) == 0) return;
     const int rb = bm.y, t = threadIdx.x;
     const int tpr = d.tpr, rsub = t / tpr, tc = t % tpr, rg = NT / tpr;
-    T *W = reinterpret_cast<T *>(d.W);
+    const gptr<T> W = glb(reinterpret_cast<T *>(d.W));
     const int64_t ldw = d.ldw;
-    const int r0 = rb * d.R, r1 = min(n, r0 + d.R);
+    const int r0 = rb * d.R, r1 = min(n, r0 + d.R), nrows = r1 - r0;
+    const int nch = (n + tpr * VE - 1) / (tpr * VE);
+    const gptr<BigHdr> hdr = glb(d.hdr);
+    const gptr<const int32_t> rl_old = glb(static_cast<const int32_t *>(d.rowlog)) + (size_t)(k & 1) * d.mstride;
+    const gptr<int32_t> rl_new = glb(d.rowlog) + (size_t)((k + 1) & 1) * d.mstride;
+    const gptr<const int32_t> cl_old = glb(static_cast<const int32_t *>(d.collog)) + (size_t)(k & 1) * d.mstride;
+    const gptr<int32_t> cl_new = glb(d.collog) + (size_t)((k + 1) & 1) * d.mstride;
+
+    // The step's critical path is: candidate list -> reduction -> pivot row
+    // -> scaled pivot row -> sweep.  Everything that does not depend on the
+    // winner is requested up front, next to the candidates: the header, the
+    // previous step's record, and the index maps of the owned rows and
+    // columns.  The memory counter retires in order and the compiler can only
+    // count loads that are issued on every path, so loads are unconditional
+    // with clamped addresses wherever a later wait must not cover them.
+    const int status = hdr->status;
+    const double tau_prev = hdr->tau;
+    StepRec prev;
+    prev.p = 1.0; prev.rphys = -1; prev.cphys = -1;
+    if (k > 0) prev = glb(d.steps)[k - 1];
+    const gptr<const BigPart> P = glb(static_cast<const BigPart *>(d.part)) + (size_t)(k & 1) * d.nblk;
+    const BigPart c0 = P[min(t, d.nblk - 1)];
+    const int ro_own = rl_old[r0 + min(t, nrows - 1)];   // old logical index of owned row t
+    VI co[kNch];
+#pragma unroll
+    for (int c = 0; c < kNch; ++c)   // in bounds: the maps hold ldw >= nch * tpr * VE entries
+        co[c] = *reinterpret_cast<gptr<const VI>>(cl_old + (c < nch ? c : 0) * tpr * VE + tc * VE);
 
     // ---- 1. reduce the candidates left by step k-1 (or the init kernel)
     double pa = 0.0, pv = 0.0;
     uint32_t pk = 0xFFFFFFFFu;
     int pi = -1, pj = -1;
-    {
-        const BigPart *P = d.part + (size_t)(k & 1) * d.nblk;
-        for (int x = t; x < d.nblk; x += NT) {
-            const BigPart c = P[x];
-            const uint32_t key = ((uint32_t)c.rlog << 16) | (uint32_t)c.clog;
-            if (better(c.a, key, pa, pk)) { pa = c.a; pv = c.v; pk = key; pi = c.iphys; pj = c.jphys; }
-        }
-        block_argmax<NT>(pa, pv, pk, pi, pj, s_a, s_v, s_k, s_i, s_j);
+    for (int x = t + NT; x < d.nblk; x += NT) {   // more workgroups than threads
+        const BigPart c = P[x];
+        const uint32_t key = ((uint32_t)c.rlog << 16) | (uint32_t)c.clog;
+        if (better(c.a, key, pa, pk)) { pa = c.a; pv = c.v; pk = key; pi = c.iphys; pj = c.jphys; }
     }
+    if (status != 0) return;
+    if (t < d.nblk) {
+        // the fold order does not matter: candidates of different
+        // workgroups have different keys
+        const uint32_t key = ((uint32_t)c0.rlog << 16) | (uint32_t)c0.clog;
+        if (better(c0.a, key, pa, pk)) { pa = c0.a; pv = c0.v; pk = key; pi = c0.iphys; pj = c0.jphys; }
+    }
+    block_argmax<NT>(pa, pv, pk, pi, pj, s_a, s_v, s_k, s_i, s_j);
     double tau;
     if (k == 0) {
         tau = (zero_tol >= 0.0) ? (double)(T)zero_tol : (double)((T)n * (T)eps_default * (T)pa);
-        if (rb == 0 && t == 0) d.hdr->tau = tau;
+        if (rb == 0 && t == 0) hdr->tau = tau;
     } else {
-        tau = d.hdr->tau;
+        tau = tau_prev;
     }
     const bool stop_nf = !(pa <= 1.7976931348623157e308);
     // (a winner without a position cannot occur for k < n; refusing it keeps
@@ -177,77 +231,102 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const bool stop_sing = (pa == 0.0) || ((T)pa < (T)tau) || pi < 0 || pj < 0;
     if (stop_nf || stop_sing) {
         if (rb == 0 && t == 0) {
-            d.hdr->status = stop_nf ? GJ_RES_NONFINITE : GJ_RES_SINGULAR;
-            d.hdr->rank = k;
+            hdr->status = stop_nf ? GJ_RES_NONFINITE : GJ_RES_SINGULAR;
+            hdr->rank = k;
         }
         return;
     }
     const int rlog = (int)(pk >> 16), clog = (int)(pk & 0xFFFFu);
     const int rp = pi, cp = pj;
     const T p = (T)pv;
+
+    // ---- 2. the winner's row and the owned rows' multipliers (eq. 15),
+    //         then the first group of owned rows (they do not depend on the
+    //         winner; requested after it so that they do not delay it)
+    const gptr<const T> Wp = W + (int64_t)rp * ldw;
+    VT pw[kNch];
+#pragma unroll
+    for (int c = 0; c < kNch; ++c)
+        pw[c] = *reinterpret_cast<gptr<const VT>>(Wp + (c < nch ? c : 0) * tpr * VE + tc * VE);
+    T q_own = W[(int64_t)(r0 + min(t, nrows - 1)) * ldw + cp];
+    constexpr int B = kRowGroup<NT>;
+    VT wb[B][kNch];
+    const bool early = kEarlyRows<NT> && !det_only;
+    if constexpr (kEarlyRows<NT>) {
+        // rows not owned, the pivot row (written at step k+1) and every row
+        // in det_only mode read row r0 instead, and are not used
+#pragma unroll
+        for (int g = 0; g < B; ++g) {
+            const int x = rsub + g * rg;
+            const bool use = early && x < nrows && r0 + x != rp;
+            const gptr<const T> Wi = W + (int64_t)(use ? r0 + x : r0) * ldw;
+#pragma unroll
+            for (int c = 0; c < kNch; ++c)
+                wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + (c < nch ? c : 0) * tpr * VE + tc * VE));
+        }
+    }
     if (rb == 0 && t == 0) {
         StepRec s;
         s.p = pv; s.rphys = rp; s.cphys = cp; s.rlog = rlog; s.clog = clog;
-        d.steps[k] = s;
+        glb(d.steps)[k] = s;
     }
-    int rpp = -1, cpp = -1;
-    T pp = (T)1;
-    if (k > 0) {
-        const StepRec s = d.steps[k - 1];
-        rpp = s.rphys; cpp = s.cphys; pp = (T)s.p;
-    }
+    const int rpp = prev.rphys, cpp = prev.cphys;
+    const T pp = (T)prev.p;
     const T y = Num<T>::one() / p, yp = Num<T>::one() / pp;   // RN(1/p): div_pivot seeds
     const bool p_ok = div_pivot_ok(p), pp_ok = div_pivot_ok(pp);
 
-    // ---- 2. multipliers of the owned rows (the pivot column, eq. 15) and
-    //         their new logical row indices
-    const int32_t *rl_old = d.rowlog + (size_t)(k & 1) * d.mstride;
-    int32_t *rl_new = d.rowlog + (size_t)((k + 1) & 1) * d.mstride;
-    for (int x = t; x < r1 - r0; x += NT) {
-        const int i = r0 + x;
-        T q = W[(int64_t)i * ldw + cp];
+    // multipliers and new logical row indices of the owned rows
+    if (t < nrows) {
+        const int i = r0 + t;
+        T q = q_own;
         if (i == rpp) q = div_pivot(q, pp, yp, pp_ok);   // deferred eq. 14 of the previous step
-        s_q[x] = q;
-        const int ro = rl_old[i];
+        s_q[t] = q;
+        const int ro = ro_own;
         const int rn = (i == rp) ? k : ((ro == k) ? rlog : ro);
-        s_rl[x] = (det_only && ro < k) ? -1 : rn;   // -1: row not needed
+        s_rl[t] = (det_only && ro < k) ? -1 : rn;   // -1: row not needed
         rl_new[i] = rn;
     }
 
     // ---- 3. the pivot row divided by the pivot (eq. 14) and the new logical
     //         column indices, for this thread's columns
-    const int32_t *cl_old = d.collog + (size_t)(k & 1) * d.mstride;
-    int32_t *cl_new = d.collog + (size_t)((k + 1) & 1) * d.mstride;
-    const int nch = (n + tpr * VE - 1) / (tpr * VE);
-    const T *Wp = W + (int64_t)rp * ldw;
     T prow[kNch][VE];
     int ckey[kNch][VE];
-    const T one = Num<T>::one();
+    bool slow = false;
 #pragma unroll
     for (int c = 0; c < kNch; ++c) {
-        if (c < nch) {
-            const int j0 = c * tpr * VE + tc * VE;
-            const VT pw = *reinterpret_cast<const VT *>(Wp + j0);
-            VI co;
-            if (j0 + VE <= n) {
-                co = *reinterpret_cast<const VI *>(cl_old + j0);
-            } else {
-#pragma unroll
-                for (int e = 0; e < VE; ++e) vset<VI, int>(co, e, (j0 + e < n) ? cl_old[j0 + e] : -1);
-            }
+        const int j0 = c * tpr * VE + tc * VE;
+        if (c < nch) {   // the same for the whole workgroup: a scalar branch
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
                 const int j = j0 + e;
-                const int o = vget<VI, int>(co, e);
+                const int o = vget<VI, int>(co[c], e);
                 const int cn = (j == cp) ? k : ((o == k) ? clog : o);
                 ckey[c][e] = (j < n) ? cn : -1;
-                prow[c][e] = (j == cp) ? y : div_pivot(vget<VT, T>(pw, e), p, y, p_ok);
-                if (rb == 0 && rsub == 0 && j < n) cl_new[j] = cn;
+                const T qv = div_pivot_fast(vget<VT, T>(pw[c], e), p, y, p_ok, slow);
+                prow[c][e] = (j == cp) ? y : qv;
             }
         } else {
 #pragma unroll
             for (int e = 0; e < VE; ++e) { ckey[c][e] = -1; prow[c][e] = (T)0; }
         }
+    }
+    if (slow) {   // operands outside the corrected-quotient range: IEEE division
+#pragma unroll
+        for (int c = 0; c < kNch; ++c)
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+                const int j = c * tpr * VE + tc * VE + e;
+                if (c < nch && j != cp) prow[c][e] = div_pivot(vget<VT, T>(pw[c], e), p, y, p_ok);
+            }
+    }
+    if (rb == 0 && rsub == 0) {
+#pragma unroll
+        for (int c = 0; c < kNch; ++c)
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+                const int j = c * tpr * VE + tc * VE + e;
+                if (c < nch && j < n) cl_new[j] = ckey[c][e];
+            }
     }
     __syncthreads();
 
@@ -256,38 +335,96 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     uint32_t bk = 0xFFFFFFFFu;
     int bi = -1, bj = -1;
     bool nf = false;
-    for (int x = rsub; x < r1 - r0; x += rg) {
-        const int i = r0 + x;
-        const int rn = s_rl[x];
-        if (i == rp || rn < 0) continue;   // pivot row: written at step k+1
-        const T q = s_q[x];
-        const bool fix = (i == rpp);
-        const bool rcand = rn > k;
-        T *Wi = W + (int64_t)i * ldw;
+    // later groups (and the first one in det_only mode): rows that are not
+    // needed are not requested
+    auto load_group = [&](int xg) {
 #pragma unroll
-        for (int c = 0; c < kNch; ++c) {
-            if (c < nch) {
-                const int j0 = c * tpr * VE + tc * VE;
-                VT w = *reinterpret_cast<const VT *>(Wi + j0);
+        for (int g = 0; g < B; ++g) {
+            const int x = xg + g * rg;
+            if (x < nrows && s_rl[x] >= 0 && r0 + x != rp) {
+                const gptr<const T> Wi = W + (int64_t)(r0 + x) * ldw;
 #pragma unroll
-                for (int e = 0; e < VE; ++e) {
-                    const int j = j0 + e;
-                    T cur = vget<VT, T>(w, e);
-                    if (fix) cur = (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok);
-                    if (j == cp) cur = (T)0;
-                    const T nv = Num<T>::fma_(-q, prow[c][e], cur);
-                    vset<VT, T>(w, e, nv);
-                    const int cl = ckey[c][e];
-                    if (rcand && cl > k) {
-                        const double an = fabs((double)nv);
-                        nf |= !(an <= 1.7976931348623157e308);
-                        const uint32_t key = ((uint32_t)rn << 16) | (uint32_t)cl;
-                        if (better(an, key, ba, bk)) { ba = an; bv = (double)nv; bk = key; bi = i; bj = j; }
-                    }
-                }
-                *reinterpret_cast<VT *>(Wi + j0) = w;
+                for (int c = 0; c < kNch; ++c)
+                    if (c < nch) wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + c * tpr * VE + tc * VE));
             }
         }
+    };
+    if (kEarlyRows<NT> && !early) load_group(rsub);
+    for (int xg = rsub; xg < nrows; xg += B * rg) {
+#pragma unroll
+        for (int g = 0; g < B; ++g) {
+            const int x = xg + g * rg;
+            if (x >= nrows) continue;
+            const int i = r0 + x;
+            const int rn = s_rl[x];
+            if (i == rp || rn < 0) continue;   // pivot row: written at step k+1
+            const T q = s_q[x];
+            const bool fix = (i == rpp);
+            const bool rcand = rn > k;
+            const uint32_t rkey = (uint32_t)rn << 16;
+            const gptr<T> Wi = W + (int64_t)i * ldw;
+            // eq. 15 for one element, then the branch-free candidate update
+            // (nearly every lane takes part, so selects beat branches)
+            auto update = [&](T cur, int c, int e, int j) -> T {
+                cur = (j == cp) ? (T)0 : cur;
+                const T nv = Num<T>::fma_(-q, prow[c][e], cur);
+                const int cl = ckey[c][e];
+                const bool cand = rcand & (cl > k);   // '&', '|': no short-circuit branches
+                const double an = fabs((double)nv);
+                nf |= cand & !(an <= 1.7976931348623157e308);
+                const uint32_t key = rkey | (uint32_t)cl;
+                const bool upd = cand & ((an > ba) | ((an == ba) & (key < bk)));
+                ba = upd ? an : ba;
+                bv = upd ? (double)nv : bv;
+                bk = upd ? key : bk;
+                bi = upd ? i : bi;
+                bj = upd ? j : bj;
+                return nv;
+            };
+            if constexpr (kEarlyRows<NT>) {
+                if (fix) {   // the previous pivot row: its deferred eq. 14 first
+#pragma unroll
+                    for (int c = 0; c < kNch; ++c)
+#pragma unroll
+                        for (int e = 0; e < VE; ++e) {
+                            const int j = c * tpr * VE + tc * VE + e;
+                            const T cur = vget<VT, T>(wb[g][c], e);
+                            vset<VT, T>(wb[g][c], e, (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok));
+                        }
+                }
+                // the whole row is updated in place in wb before any of it is
+                // stored: a store's data registers cannot be reused until the
+                // store has completed, so a register shared by all chunks
+                // would serialise them
+#pragma unroll
+                for (int c = 0; c < kNch; ++c)
+                    if (c < nch)
+#pragma unroll
+                        for (int e = 0; e < VE; ++e)
+                            vset<VT, T>(wb[g][c], e,
+                                        update(vget<VT, T>(wb[g][c], e), c, e, c * tpr * VE + tc * VE + e));
+#pragma unroll
+                for (int c = 0; c < kNch; ++c)
+                    if (c < nch) row_st(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < kNch; ++c) {
+                    if (c < nch) {
+                        const int j0 = c * tpr * VE + tc * VE;
+                        VT w = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + j0));
+#pragma unroll
+                        for (int e = 0; e < VE; ++e) {
+                            const int j = j0 + e;
+                            T cur = vget<VT, T>(w, e);
+                            if (fix) cur = (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok);
+                            vset<VT, T>(w, e, update(cur, c, e, j));
+                        }
+                        row_st(reinterpret_cast<gptr<VT>>(Wi + j0), w);
+                    }
+                }
+            }
+        }
+        if (kEarlyRows<NT> && xg + B * rg < nrows) load_group(xg + B * rg);
     }
     if (k + 1 < n) {
         const int any_nf = __syncthreads_or(nf ? 1 : 0);
@@ -300,7 +437,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
             o.clog = (int32_t)(bk & 0xFFFFu);
             o.iphys = bi;
             o.jphys = bj;
-            d.part[(size_t)((k + 1) & 1) * d.nblk + rb] = o;
+            glb(d.part)[(size_t)((k + 1) & 1) * d.nblk + rb] = o;
         }
     }
 }
@@ -391,7 +528,7 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int NT>
+template <typename T, int NT, bool NTL>
 static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDesc &single,
                             const int *grid_per_step,
                             int grid_init, int grid_finish, int max_n, int gather_grid,
@@ -405,7 +542,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         if (e != hipSuccess) return e;
     }
     for (int k = 0; k < max_n; ++k) {
-        hipLaunchKernelGGL((gj_big_step<T, NT>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
+        hipLaunchKernelGGL((gj_big_step<T, NT, NTL>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
                            dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only,
                            run_flag);
         e = hipGetLastError();
@@ -425,13 +562,17 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
     return e;
 }
 
-hipError_t launch_big(bool fp32, int nt, const BigDesc *descs, const int2 *bmap,
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, const BigDesc *descs, const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
                       void *const *events, const int32_t *run_flag, hipStream_t s) {
-#define GJ_BIG_CASE(TT, NTV)                                                                \
-    return run_big_t<TT, NTV>(descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n,   \
-                              gather_grid, zero_tol, eps_default, det_only, events, run_flag, s)
+#define GJ_BIG_CASE(TT, NTV)                                                                    \
+    return nt_loads ? run_big_t<TT, NTV, true>(descs, bmap, single, grid_per_step, grid_init,      \
+                                               grid_finish, max_n, gather_grid, zero_tol,          \
+                                               eps_default, det_only, events, run_flag, s)         \
+                    : run_big_t<TT, NTV, false>(descs, bmap, single, grid_per_step, grid_init,     \
+                                                grid_finish, max_n, gather_grid, zero_tol,         \
+                                                eps_default, det_only, events, run_flag, s)
     if (fp32) {
         switch (nt) {
             case 256: GJ_BIG_CASE(float, 256);

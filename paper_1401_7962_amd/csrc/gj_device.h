@@ -62,6 +62,19 @@ __device__ inline bool div_pivot_ok(T p) {
     return ap >= DivRange<T>::lo() && ap <= DivRange<T>::hi();
 }
 
+// Straight-line part of div_pivot: the corrected quotient, and `slow` set
+// when x lies outside the range where the correction is exact (the caller
+// then redoes those elements with div_pivot, off the common path).
+template <typename T>
+__device__ __forceinline__ T div_pivot_fast(T x, T p, T y, bool p_ok, bool &slow) {
+    const T ax = Num<T>::abs_(x);
+    const T q = x * y;
+    const T r = Num<T>::fma_(-p, q, x);
+    const T res = (ax == (T)0) ? q : Num<T>::fma_(r, y, q);
+    slow |= !((ax == (T)0) || (p_ok && ax >= DivRange<T>::lo() && ax <= DivRange<T>::hi()));
+    return res;
+}
+
 template <typename T>
 __device__ inline T div_pivot(T x, T p, T y, bool p_ok) {
     const T ax = Num<T>::abs_(x);
@@ -252,6 +265,18 @@ struct BigHdr {
     int32_t rank;
     double tau;
 };
+
+// Global-address-space views of device pointers.  Pointers read from a
+// descriptor are generic to the compiler, which then emits FLAT accesses; a
+// FLAT load counts against the LDS counter too, so every LDS wait would also
+// wait for it.  Accesses through these views compile to global_load/store.
+// (The host pass only type-checks kernel bodies; it sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using gptr = __attribute__((address_space(1))) T *;
+#else
+template <typename T> using gptr = T *;
+#endif
+template <typename T> __device__ __forceinline__ gptr<T> glb(T *p) { return (gptr<T>)p; }
 
 struct BigDesc {
     void *W;              // T[n x ldw]
