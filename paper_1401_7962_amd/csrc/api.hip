@@ -49,11 +49,15 @@ bool read_opts(const gj_opts *o, Opts &out) {
     return true;
 }
 
+}  // namespace
+
 int env_int(const char *name, int dflt) {
     const char *v = std::getenv(name);
     if (!v || !*v) return dflt;
     return std::atoi(v);
 }
+
+namespace {
 
 // ------------------------------------------------------------ tuning table
 // Written by the project's autotuner (paper_1401_7962_amd/tune.py) as lines

@@ -7,6 +7,9 @@ namespace gj {
 
 hipError_t launch_zero_u32(uint32_t *p, int count, hipStream_t s);
 
+// integer environment override (dflt when unset or unparsable)
+int env_int(const char *name, int dflt);
+
 // on-chip task classes for batches: 0 = (kind 0, E 8, n in 65..128),
 // 1..4 = (kind 1, E 8/4/2/1, n in 33..64 / 17..32 / 9..16 / 1..8)
 constexpr int kOnchipClasses = 5;

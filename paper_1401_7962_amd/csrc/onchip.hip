@@ -44,6 +44,7 @@ struct CoreLds {
     int32_t ip[N]; // pivot sequence, written out once at the end (a global
     int32_t jp[N]; // store inside the step loop would make every barrier wait for it)
     Cand<T> red[NW];
+    T pv;          // the signed pivot of the current step (for the determinant)
 };
 
 template <int NW>
@@ -77,11 +78,12 @@ __device__ inline void group_argmax(Cand<T> &c, CoreLds<T, N, NW> &L, int t) {
 
 // Scan this thread's part of the trailing block (rows and columns > k) in
 // row-major order; strict '>' keeps the first maximum (padding holds 0 and
-// never wins).  Register blocks
-// whose rows (or columns) are all pivoted already are skipped: the test is
-// the same for the whole wavefront.  The winning slot is tracked as the
-// compile-time code a*EB+b so that no per-element key stays live across
-// steps.
+// never wins).  Register blocks whose rows (or columns) are all pivoted are
+// skipped: the test is the same for the whole wavefront.  The candidate
+// carries |a| and the position; the owners of the winning row recover the
+// signed pivot when they stage it.  The winning slot is tracked as the
+// compile-time code a*EB+b, so no per-element key stays live across steps,
+// and the lane masks are combined with '&' (no short-circuit branches).
 template <typename T, int TR, int TC, int EA, int EB>
 __device__ __forceinline__ void scan_argmax(const T (&v)[EA][EB], int k, int tr, int tc,
                                             Cand<T> &c) {
@@ -89,33 +91,36 @@ __device__ __forceinline__ void scan_argmax(const T (&v)[EA][EB], int k, int tr,
     bool cok[EB];
 #pragma unroll
     for (int b = 0; b < EB; ++b) cok[b] = (b * TC + tc > k);
-    // one running maximum per register row (independent chains), each kept
-    // with strict '>' so that it holds the row's first maximum
-    T rbest[EA];
-    int rcode[EA];
+    // two running maxima (even and odd register rows: independent chains)
+    constexpr int NCH = EA < 2 ? EA : 2;
+    T rbest[NCH];
+    int rcode[NCH];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) { rbest[h] = (T)0; rcode[h] = -1; }
 #pragma unroll
     for (int a = 0; a < EA; ++a) {
-        rbest[a] = (T)0;
-        rcode[a] = -1;
         if (a * TR + TR - 1 <= k) continue;        // every row of this block pivoted
         const bool rok = (a * TR + tr > k);
+        const int h = a % NCH;
 #pragma unroll
         for (int b = 0; b < EB; ++b) {
             if (b * TC + TC - 1 <= k) continue;    // every column of this block pivoted
-            const T x = v[a][b];
-            const bool gt = rok && cok[b] && (M::abs_(x) > M::abs_(rbest[a]));
-            rbest[a] = gt ? x : rbest[a];
-            rcode[a] = gt ? (a * EB + b) : rcode[a];
+            const T ax = M::abs_(v[a][b]);
+            const bool gt = rok & cok[b] & (ax > rbest[h]);
+            rbest[h] = gt ? ax : rbest[h];
+            rcode[h] = gt ? (a * EB + b) : rcode[h];
         }
     }
-    // rows in increasing order, strict '>': the first maximum in row-major order
+    // merge the chains: on equal values the smaller slot code (earlier in
+    // row-major order) wins
     T best = rbest[0];
     int code = rcode[0];
 #pragma unroll
-    for (int a = 1; a < EA; ++a) {
-        const bool gt = M::abs_(rbest[a]) > M::abs_(best);
-        best = gt ? rbest[a] : best;
-        code = gt ? rcode[a] : code;
+    for (int h = 1; h < NCH; ++h) {
+        const bool gt = (rbest[h] > best) | ((rbest[h] == best) & (rcode[h] >= 0) &
+                                               ((unsigned)rcode[h] < (unsigned)code));
+        best = gt ? rbest[h] : best;
+        code = gt ? rcode[h] : code;
     }
     c.v = best;
     const int i = (code / EB) * TR + tr, j = (code % EB) * TC + tc;
@@ -182,99 +187,131 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
     int code = GJ_RES_OK, rank = n;
 
     for (int k = 0; k < n; ++k) {
-        const T m = M::abs_(c.v);
+        const T m = c.v;   // |pivot|
         if (nf || !M::finite_(m)) { code = GJ_RES_NONFINITE; rank = k; break; }
         if (m == (T)0 || m < tau) { code = GJ_RES_SINGULAR; rank = k; break; }
         const int r = (int)(c.key >> 16), cc = (int)(c.key & 0xFFFFu);
-        const T p = c.v;
-        det.mul(p);
-        if (r != k) det.sign = -det.sign;
-        if (cc != k) det.sign = -det.sign;
         const int ar = r / TR, trr = r % TR, ak = k / TR, trk = k % TR;
         const int bc = cc / TC, tcc = cc % TC, bk = k / TC, tck = k % TC;
-        const T one = M::one();
-        const T y = one / p;                   // RN(1/p): the pivot slot, and div_pivot's seed
-        const bool p_ok = div_pivot_ok(p);
 
-        // stage the four swapped lines and the scaled pivot row (eq. 14)
+        // stage the four swapped lines and the scaled pivot row (eq. 14).
+        // Row r: its owners extract it (uniform branches on ar), take the
+        // signed pivot from the lane that holds column c, and divide.
         if (tr == trr) {
 #pragma unroll
-            for (int a = 0; a < EA; ++a) if (a == ar) {
+            for (int a = 0; a < EA; ++a)
+                if (a == ar) {
+                    T xc = (T)0;
 #pragma unroll
-                for (int b = 0; b < EB; ++b) {
-                    const int jo = b * TC + tc;
-                    const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
-                    L.prow[jn] = (jo == cc) ? y : div_pivot(v[a][b], p, y, p_ok);
+                    for (int b = 0; b < EB; ++b)
+                        if (b == bc) xc = v[a][b];
+                    // the pivot sits in lane (trr, tcc) of this row group
+                    const int src = (trr * TC + tcc) & (kWave - 1);
+                    T p;
+                    if constexpr (sizeof(T) == 8) {
+                        const int lo = __builtin_amdgcn_readlane(__double2loint(xc), src);
+                        const int hi = __builtin_amdgcn_readlane(__double2hiint(xc), src);
+                        p = __hiloint2double(hi, lo);
+                    } else {
+                        p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xc), src));
+                    }
+                    if (tc == tcc) L.pv = p;
+                    const T y = M::one() / p;   // RN(1/p): the pivot slot, and the division seed
+                    const bool p_ok = div_pivot_ok(p);
+                    bool slow = false;
+#pragma unroll
+                    for (int b = 0; b < EB; ++b) {
+                        const int jo = b * TC + tc;
+                        const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
+                        const T qv = div_pivot_fast(v[a][b], p, y, p_ok, slow);
+                        L.prow[jn] = (jo == cc) ? y : qv;
+                    }
+                    if (slow) {   // operands outside the corrected-quotient range
+#pragma unroll
+                        for (int b = 0; b < EB; ++b) {
+                            const int jo = b * TC + tc;
+                            const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
+                            if (jo != cc) L.prow[jn] = div_pivot(v[a][b], p, y, p_ok);
+                        }
+                    }
                 }
-            }
         }
         if (tr == trk) {
 #pragma unroll
-            for (int a = 0; a < EA; ++a) if (a == ak) {
+            for (int a = 0; a < EA; ++a)
+                if (a == ak) {
 #pragma unroll
-                for (int b = 0; b < EB; ++b) {
-                    const int jo = b * TC + tc;
-                    const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
-                    L.newr[jn] = v[a][b];
+                    for (int b = 0; b < EB; ++b) {
+                        const int jo = b * TC + tc;
+                        const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
+                        L.newr[jn] = v[a][b];
+                    }
                 }
-            }
         }
         if (tc == tcc) {
 #pragma unroll
-            for (int b = 0; b < EB; ++b) if (b == bc) {
+            for (int b = 0; b < EB; ++b)
+                if (b == bc) {
 #pragma unroll
-                for (int a = 0; a < EA; ++a) {
-                    const int io = a * TR + tr;
-                    const int in = (io == r) ? k : ((io == k) ? r : io);
-                    L.pcol[in] = v[a][b];
+                    for (int a = 0; a < EA; ++a) {
+                        const int io = a * TR + tr;
+                        const int in = (io == r) ? k : ((io == k) ? r : io);
+                        L.pcol[in] = v[a][b];
+                    }
                 }
-            }
         }
         if (tc == tck) {
 #pragma unroll
-            for (int b = 0; b < EB; ++b) if (b == bk) {
+            for (int b = 0; b < EB; ++b)
+                if (b == bk) {
 #pragma unroll
-                for (int a = 0; a < EA; ++a) {
-                    const int io = a * TR + tr;
-                    const int in = (io == r) ? k : ((io == k) ? r : io);
-                    L.newc[in] = v[a][b];
+                    for (int a = 0; a < EA; ++a) {
+                        const int io = a * TR + tr;
+                        const int in = (io == r) ? k : ((io == k) ? r : io);
+                        L.newc[in] = v[a][b];
+                    }
                 }
-            }
         }
         group_sync<NW>();
 
-        // bookkeeping off the critical path: pivots and the depivoting maps
+        // bookkeeping off the critical path: pivots, depivoting maps and the
+        // determinant (eq. 13)
         if (t == 0) {
             L.ip[k] = r;
             L.jp[k] = cc;
             int tmp = L.g[k]; L.g[k] = L.g[cc]; L.g[cc] = tmp;
             tmp = L.h[k]; L.h[k] = L.h[r]; L.h[r] = tmp;
+            det.mul(L.pv);
+            if (r != k) det.sign = -det.sign;
+            if (cc != k) det.sign = -det.sign;
         }
 
         // install the swapped row r and column c; clear column k (it becomes
         // fma(-q, 1/p, 0) below, the D column of eq. 15)
         if (tr == trr) {
 #pragma unroll
-            for (int a = 0; a < EA; ++a) if (a == ar) {
+            for (int a = 0; a < EA; ++a)
+                if (a == ar) {
 #pragma unroll
-                for (int b = 0; b < EB; ++b) v[a][b] = L.newr[b * TC + tc];
-            }
+                    for (int b = 0; b < EB; ++b) v[a][b] = L.newr[b * TC + tc];
+                }
         }
         if (tc == tcc) {
 #pragma unroll
-            for (int b = 0; b < EB; ++b) if (b == bc) {
+            for (int b = 0; b < EB; ++b)
+                if (b == bc) {
 #pragma unroll
-                for (int a = 0; a < EA; ++a) v[a][b] = L.newc[a * TR + tr];
-            }
+                    for (int a = 0; a < EA; ++a) v[a][b] = L.newc[a * TR + tr];
+                }
         }
         if (tc == tck) {
 #pragma unroll
-            for (int b = 0; b < EB; ++b) if (b == bk) {
+            for (int b = 0; b < EB; ++b)
+                if (b == bk) {
 #pragma unroll
-                for (int a = 0; a < EA; ++a) v[a][b] = (T)0;
-            }
+                    for (int a = 0; a < EA; ++a) v[a][b] = (T)0;
+                }
         }
-
         // eq. 15 for every row, then the pivot row takes its scaled values
         T q[EA], pr[EB];
 #pragma unroll
@@ -287,12 +324,12 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
             for (int b = 0; b < EB; ++b) v[a][b] = M::fma_(-q[a], pr[b], v[a][b]);
         if (tr == trk) {
 #pragma unroll
-            for (int a = 0; a < EA; ++a) if (a == ak) {
+            for (int a = 0; a < EA; ++a)
+                if (a == ak) {
 #pragma unroll
-                for (int b = 0; b < EB; ++b) v[a][b] = pr[b];
-            }
+                    for (int b = 0; b < EB; ++b) v[a][b] = pr[b];
+                }
         }
-
         // fused pivot search for step k+1 over rows and columns > k
         if (k + 1 < n) {
             scan_argmax<T, TR, TC, EA, EB>(v, k, tr, tc, c);
@@ -426,6 +463,8 @@ static hipError_t launch_cls(const MatDesc *mats, const OnchipTask *tasks, int n
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gj_onchip_kernel<T, KIND, E>, 256, 0) != hipSuccess) per = 1;
+        const int force = env_int("GJ_ONCHIP_PER_CU", 0);   // experiments only
+        if (force > 0) per = force;
         grid = std::max(1, std::min(ntasks, cus * std::max(per, 1)));
     }
     hipLaunchKernelGGL((gj_onchip_kernel<T, KIND, E>), dim3(grid), dim3(256), 0, s, mats, tasks,
