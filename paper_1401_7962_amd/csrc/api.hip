@@ -526,6 +526,29 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
             g1.D = T; g1.ldd = n;
             g1.alpha = 1.0; g1.run_flag = fdet;
             GJ_TRY(launch_gemm_f64(g1, s));
+            // one refinement step of the block solve T = D^-1 S12 (S12 is not
+            // needed afterwards and takes the residual): with the explicit
+            // inverse alone the Schur complement, and so log|det|, carries an
+            // error of order cond(D) u; the corrected T makes it as accurate
+            // as an LU in the same order
+            GemmArgs gr;
+            std::memset(&gr, 0, sizeof(gr));
+            gr.M = nbk; gr.N = mm; gr.K = nbk;
+            gr.A = B + (int64_t)kb * n + kb; gr.lda = n;
+            gr.B = T; gr.ldb = n;
+            gr.C = B + (int64_t)kb * n + kb + nbk; gr.ldc = n;
+            gr.D = const_cast<double *>(gr.C); gr.ldd = n;
+            gr.alpha = -1.0; gr.beta = 1.0; gr.run_flag = fdet;
+            GJ_TRY(launch_gemm_f64(gr, s));
+            GemmArgs gc;
+            std::memset(&gc, 0, sizeof(gc));
+            gc.M = nbk; gc.N = mm; gc.K = nbk;
+            gc.A = Dinv; gc.lda = kDetBlock;
+            gc.B = gr.C; gc.ldb = n;
+            gc.C = T; gc.ldc = n;
+            gc.D = T; gc.ldd = n;
+            gc.alpha = 1.0; gc.beta = 1.0; gc.run_flag = fdet;
+            GJ_TRY(launch_gemm_f64(gc, s));
             GemmArgs g2;
             std::memset(&g2, 0, sizeof(g2));
             g2.M = mm; g2.N = mm; g2.K = nbk;
@@ -616,7 +639,7 @@ struct RefBatchPlan {
     GemmList r0, upd[2], res[2];
     // determinant block steps
     std::vector<OnchipSet> det_blocks;
-    std::vector<GemmList> det_t, det_s;
+    std::vector<GemmList> det_t, det_r, det_c, det_s;   // T, residual, correction, Schur update
     size_t total = 0;
 };
 
@@ -683,6 +706,8 @@ bool plan_refined_batch(int batch, const int32_t *n_host, RefBatchPlan &P) {
     const int nsteps = (maxn + kDetBlock - 1) / kDetBlock;
     P.det_blocks.resize(nsteps);
     P.det_t.resize(nsteps);
+    P.det_r.resize(nsteps);
+    P.det_c.resize(nsteps);
     P.det_s.resize(nsteps);
     auto list_bytes = [&](GemmList &L, int count_probs, int count_tiles) {
         L.off_probs = c; c = a256(c + sizeof(GemmArgs) * std::max(1, count_probs));
@@ -707,6 +732,8 @@ bool plan_refined_batch(int batch, const int32_t *n_host, RefBatchPlan &P) {
         P.det_blocks[s].off_mats = c; c = a256(c + sizeof(MatDesc) * std::max(1, nmat));
         P.det_blocks[s].off_tasks = c; c = a256(c + sizeof(OnchipTask) * std::max(1, nmat));
         list_bytes(P.det_t[s], nprob, tt);
+        list_bytes(P.det_r[s], nprob, tt);
+        list_bytes(P.det_c[s], nprob, tt);
         list_bytes(P.det_s[s], nprob, ts);
     }
     P.total = c;
@@ -829,6 +856,25 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
                 g1.D = Tb; g1.ldd = n;
                 g1.alpha = 1.0; g1.run_flag = ctl_run_det(cm);
                 P.det_t[st].add(g1);
+                // one refinement step of T (see the single-matrix path)
+                GemmArgs gr;
+                std::memset(&gr, 0, sizeof(gr));
+                gr.M = nbk; gr.N = mm; gr.K = nbk;
+                gr.A = Bb + (int64_t)kb * n + kb; gr.lda = n;
+                gr.B = Tb; gr.ldb = n;
+                gr.C = Bb + (int64_t)kb * n + kb + nbk; gr.ldc = n;
+                gr.D = const_cast<double *>(gr.C); gr.ldd = n;
+                gr.alpha = -1.0; gr.beta = 1.0; gr.run_flag = ctl_run_det(cm);
+                P.det_r[st].add(gr);
+                GemmArgs gc;
+                std::memset(&gc, 0, sizeof(gc));
+                gc.M = nbk; gc.N = mm; gc.K = nbk;
+                gc.A = g1.A; gc.lda = ldd;
+                gc.B = gr.C; gc.ldb = n;
+                gc.C = Tb; gc.ldc = n;
+                gc.D = Tb; gc.ldd = n;
+                gc.alpha = 1.0; gc.beta = 1.0; gc.run_flag = ctl_run_det(cm);
+                P.det_c[st].add(gc);
                 GemmArgs g2;
                 std::memset(&g2, 0, sizeof(g2));
                 g2.M = mm; g2.N = mm; g2.K = nbk;
@@ -867,6 +913,8 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
             put(P.det_blocks[st].off_mats, P.det_blocks[st].mats.data(), sizeof(MatDesc) * P.det_blocks[st].mats.size());
             put(P.det_blocks[st].off_tasks, P.det_blocks[st].tasks.data(), sizeof(OnchipTask) * P.det_blocks[st].tasks.size());
             put_list(P.det_t[st]);
+            put_list(P.det_r[st]);
+            put_list(P.det_c[st]);
             put_list(P.det_s[st]);
         }
         for (auto &u : up)
@@ -948,6 +996,8 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
                             reinterpret_cast<int32_t *>(w) + kDetBlock, blockres, -1.0, kEps64);
         if (st != GJ_OK) return st;
         if ((st = grouped(P.det_t[sb])) != GJ_OK) return st;
+        if ((st = grouped(P.det_r[sb])) != GJ_OK) return st;
+        if ((st = grouped(P.det_c[sb])) != GJ_OK) return st;
         if ((st = grouped(P.det_s[sb])) != GJ_OK) return st;
     }
     GJ_TRY(launch_det_combine(memd, RefMember(), ctl, batch, s));

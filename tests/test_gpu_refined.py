@@ -10,7 +10,9 @@ Bars (tolerances derived in the design doc):
 * the Newton-Schulz update count is within one of the oracle's loop run from
   the same FP32 starting inverse;
 * the FP64 determinant agrees with the static-pivot LU oracle (same pivot
-  order) and with the closed form n ln(cond) / 2 of the test matrices.
+  order) to 1e-11 relative in log|det| (both are backward stable in that
+  order; measured at most 3e-13 up to cond 1e8), and with the closed form
+  n ln(cond) / 2 of the test matrices.
 """
 import numpy as np
 import pytest
@@ -68,7 +70,7 @@ def test_refined_inverse(gj, n, cond):
     # FP64 determinant
     lu = oracle.lu_static_det_f64(A, i32, j32)
     assert r["det_sign"] == lu["det_sign"] == 1
-    assert abs(r["logabsdet"] - lu["logabsdet"]) <= max(1e-12, n * cond * 2.0 ** -53) * abs(lu["logabsdet"])
+    assert abs(r["logabsdet"] - lu["logabsdet"]) <= 1e-11 * abs(lu["logabsdet"])
     if cond <= 1e6:
         cf = inputs.closed_form_logdet(n, cond)
         assert abs(r["logabsdet"] - cf) <= 1e-9 * abs(cf)
@@ -174,4 +176,4 @@ def test_refined_batched_mixed(gj):
         assert abs(r["refine_iters"] - upd) <= 1, where
         lu = oracle.lu_static_det_f64(A, i32, j32)
         assert r["det_sign"] == lu["det_sign"], where
-        assert abs(r["logabsdet"] - lu["logabsdet"]) <= max(1e-12, n * conds[b] * 2.0 ** -53) * max(1.0, abs(lu["logabsdet"])), where
+        assert abs(r["logabsdet"] - lu["logabsdet"]) <= 1e-11 * max(1.0, abs(lu["logabsdet"])), where
