@@ -34,9 +34,15 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 // One 128 x 128 tile of D.  `b` is the tile index within the problem,
 // `part` the slot of its norm partial.
+//
+// The K loop is double-buffered in LDS: while the wavefronts multiply slice
+// kt out of one buffer, the next slice (already in registers) is written to
+// the other, and a single barrier per slice separates the two roles.  Global
+// reads go through the global address space (not FLAT), so that waiting for
+// an LDS read never waits for the prefetch of the next slice as well.
 __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
-    __shared__ double As[BK][LDA_S];  // As[k][m]
-    __shared__ double Bs[BK][LDB_S];  // Bs[k][n]
+    __shared__ double As[2][BK][LDA_S];  // As[buf][k][m]
+    __shared__ double Bs[2][BK][LDB_S];  // Bs[buf][k][n]
     __shared__ double s_red[NTH / kWave];
 
     const int tiles_n = (g.N + BN - 1) / BN;
@@ -45,6 +51,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
+    const gptr<const double> gA = glb(g.A), gB = glb(g.B);
 
     d4 acc[4][4];
 #pragma unroll
@@ -62,47 +69,45 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int gk = k0 + a_k0 + e;
-            ra[e] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.lda + gk] : 0.0;
+            ra[e] = (gm < g.M && gk < g.K) ? gA[(int64_t)gm * g.lda + gk] : 0.0;
         }
         const int gk = k0 + b_k;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int gn = n0 + b_c0 + e;
-            rb[e] = (gk < g.K && gn < g.N) ? g.B[(int64_t)gk * g.ldb + gn] : 0.0;
+            rb[e] = (gk < g.K && gn < g.N) ? gB[(int64_t)gk * g.ldb + gn] : 0.0;
         }
     };
-    auto store_tile = [&]() {
+    auto store_tile = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) As[a_k0 + e][a_row] = ra[e];
+        for (int e = 0; e < 8; ++e) As[buf][a_k0 + e][a_row] = ra[e];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[b_k][b_c0 + e] = rb[e];
+        for (int e = 0; e < 8; ++e) Bs[buf][b_k][b_c0 + e] = rb[e];
     };
 
     const int nk = (g.K + BK - 1) / BK;
     load_tile(0);
-    store_tile();
+    store_tile(0);
     __syncthreads();
     const int li = lane & 15, lk = lane >> 4;
     for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
         if (kt + 1 < nk) load_tile((kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             double fa[4], fb[4];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) fa[f] = As[kk + lk][wm * 64 + f * 16 + li];
+            for (int f = 0; f < 4; ++f) fa[f] = As[cur][kk + lk][wm * 64 + f * 16 + li];
 #pragma unroll
-            for (int f = 0; f < 4; ++f) fb[f] = Bs[kk + lk][wn * 64 + f * 16 + li];
+            for (int f = 0; f < 4; ++f) fb[f] = Bs[cur][kk + lk][wn * 64 + f * 16 + li];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
         }
+        if (kt + 1 < nk) store_tile(cur ^ 1);
         __syncthreads();
-        if (kt + 1 < nk) {
-            store_tile();
-            __syncthreads();
-        }
     }
 
     // epilogue: accumulator register r of lane l holds row l/16 + 4r, column
@@ -118,9 +123,9 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
                 const int row = m0 + wm * 64 + i * 16 + lk + 4 * r;
                 if (row < g.M && col < g.N) {
                     double v = g.alpha * acc[i][j][r];
-                    if (g.beta != 0.0) v = fma(g.beta, g.C[(int64_t)row * g.ldc + col], v);
+                    if (g.beta != 0.0) v = fma(g.beta, glb(g.C)[(int64_t)row * g.ldc + col], v);
                     if (row == col) v += g.gamma;
-                    g.D[(int64_t)row * g.ldd + col] = v;
+                    glb(g.D)[(int64_t)row * g.ldd + col] = v;
                     ssq = fma(v, v, ssq);
                 }
             }
@@ -131,11 +136,11 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
         for (int off = 32; off >= 1; off >>= 1) ssq += __shfl_xor(ssq, off, kWave);
         if (lane == 0) s_red[w] = ssq;
         __syncthreads();
-        if (t == 0) g.norm_partials[part] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+        if (t == 0) glb(g.norm_partials)[part] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
     }
 }
 
-__global__ void __launch_bounds__(NTH)
+__global__ void __launch_bounds__(NTH, 2)
 gemm_f64_kernel(const GemmArgs g) {
     if (g.run_flag && *g.run_flag == 0) return;
     const int ntiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
@@ -146,7 +151,7 @@ gemm_f64_kernel(const GemmArgs g) {
 }
 
 // Many independent products in one launch: workgroup -> (problem, tile).
-__global__ void __launch_bounds__(NTH)
+__global__ void __launch_bounds__(NTH, 2)
 gemm_f64_grouped_kernel(const GemmArgs *__restrict__ probs, const int2 *__restrict__ tilemap) {
     const int2 pt = tilemap[blockIdx.x];
     const GemmArgs g = probs[pt.x];
