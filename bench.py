@@ -318,6 +318,24 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
     d = float(torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"]))
     out["refined_vs_plain_rel_frobenius"] = d
     out["speedup_refined_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined"]["ms"], 3)
+    # roofline of the refinement's dominant kernel: the Newton-Schulz product
+    # X R (n x n x n, FP64 MFMA), timed alone with HIP events
+    X, R = Xs["fp32_refined"], Xs["plain_fp64"]
+    D = torch.empty_like(X)
+    gj.gj_dgemm(X, R, D=D)
+    torch.cuda.synchronize()
+    e = _events(2 * reps, stream)
+    for k in range(reps):
+        e[2 * k].record()
+        gj.gj_dgemm(X, R, D=D)
+        e[2 * k + 1].record()
+    torch.cuda.synchronize()
+    gms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+    tflops = 2.0 * n ** 3 / (gms * 1e-3) / 1e12
+    out["mfma_roofline"] = {"bound": "mfma", "kernel": "gemm_f64_kernel (n x n x n)",
+                            "ms": round(gms, 3), "achieved": round(tflops, 2),
+                            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(tflops / FP64_PEAK_TFLOPS, 4)}
     return out
 
 

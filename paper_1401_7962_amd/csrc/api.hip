@@ -150,6 +150,12 @@ bool big_nt_loads(size_t swept_bytes) {
 size_t big_swept_bytes(const BigShape &s, bool fp32) {
     return (size_t)s.n * (size_t)s.ldw * (fp32 ? 4 : 8);
 }
+// Every thread of the row uses all 8 of its vector chunks (the step kernel
+// then compiles without the per-chunk tests).
+bool big_full(const BigShape &s, bool fp32) {
+    const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
+    return (s.n + per - 1) / per == 8;
+}
 
 // Byte layout of one matrix's streaming-path buffers, relative to `base`.
 struct BigBufs {
@@ -212,6 +218,7 @@ struct BatchPlan {
     std::vector<int> grid_per_step;
     int big_nt = 256, big_max_n = 0;
     size_t big_swept = 0;          // bytes of W swept per step (all streaming members)
+    bool big_full = true;          // every streaming member uses all chunks
     int cls_start[kOnchipClasses] = {0}, cls_count[kOnchipClasses] = {0};
     // byte offsets in the workspace
     size_t off_mats = 0, off_tasks = 0, off_queue = 0, off_descs = 0, off_bmap = 0, total = 0;
@@ -261,6 +268,7 @@ bool plan_batch(int batch, const int32_t *n_host, bool fp32, BatchPlan &P) {
             BigShape s = big_shape(n_host[m], fp32, P.big_nt);
             P.big_shapes.push_back(s);
             P.big_swept += big_swept_bytes(s, fp32);
+            P.big_full = P.big_full && big_full(s, fp32);
             nb += s.nblk;
         }
         P.off_bmap = c; c = a256(c + sizeof(int2) * nb);
@@ -346,7 +354,8 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
     BigBufs bb = big_bufs(sh, fp32, 0);
     if (ws_bytes < bb.end) return GJ_E_WORKSPACE;
     BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
-    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), nullptr, nullptr,
+    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32),
+                              nullptr, nullptr,
                               d, nullptr, sh.nblk, sh.nblk, n,
                               det_only ? 0 : sh.nblk, o.zero_tol, eps_default, det_only ? 1 : 0,
                               o.events, nullptr, s);
@@ -436,7 +445,8 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, true, nt);
         BigBufs bb = big_bufs(sh, true, L.big32);
         d32 = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), nullptr, nullptr, d32,
+        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true),
+                          nullptr, nullptr, d32,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, 0.0, 0.0, det_only ? 1 : 0, o.events, nullptr, s));
     }
@@ -499,7 +509,8 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, false, nt);
         BigBufs bb = big_bufs(sh, false, L.over64);
         BigDesc d = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), nullptr, nullptr, d,
+        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false),
+                          nullptr, nullptr, d,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
                           ctl_run_fallback(ctl), s));
@@ -634,6 +645,7 @@ struct RefBatchPlan {
     std::vector<int> fb_grid;
     int fb_nt = 256;
     size_t fb_swept = 0;
+    bool fb_full = true;
     size_t off_fb_descs = 0, off_fb_bmap = 0;
     // Newton-Schulz product lists
     GemmList r0, upd[2], res[2];
@@ -689,6 +701,7 @@ bool plan_refined_batch(int batch, const int32_t *n_host, RefBatchPlan &P) {
             BigShape s = big_shape(n_host[m], false, P.fb_nt);
             P.fb_shapes.push_back(s);
             P.fb_swept += big_swept_bytes(s, false);
+            P.fb_full = P.fb_full && big_full(s, false);
             P.fb_bufs.push_back(big_bufs(s, false, P.region[m]));
             nb += s.nblk;
         }
@@ -950,7 +963,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)E.bmap.size();
-        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept),
+        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full,
                           reinterpret_cast<const BigDesc *>(w + E.off_descs),
                           reinterpret_cast<const int2 *>(w + E.off_bmap), BigDesc(),
                           E.grid_per_step.data(), nb, nb, E.big_max_n, nb, 0.0, 0.0, 0, o.events,
@@ -977,7 +990,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)P.fb_bmap.size();
-        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept),
+        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full,
                           reinterpret_cast<const BigDesc *>(w + P.off_fb_descs),
                           reinterpret_cast<const int2 *>(w + P.off_fb_bmap), BigDesc(),
                           P.fb_grid.data(), nb, nb, E.big_max_n, nb, o.zero_tol, kEps64, 0, nullptr,
@@ -1238,7 +1251,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         }
         if (!P.big_members.empty()) {
             const int nb = (int)P.bmap.size();
-            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept),
+            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full,
                                       reinterpret_cast<const BigDesc *>(w + P.off_descs),
                                       reinterpret_cast<const int2 *>(w + P.off_bmap), BigDesc(),
                                       P.grid_per_step.data(), nb, nb, P.big_max_n, nb, o.zero_tol,

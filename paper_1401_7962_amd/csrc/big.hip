@@ -148,7 +148,9 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 }
 
 // ------------------------------------------------------------------ step
-template <typename T, int NT, bool NTL>
+// FULL: every matrix of the launch uses all kNch chunks per thread (the
+// chunk tests then fold away; they cost about 8% at n = 4096).
+template <typename T, int NT, bool NTL, bool FULL>
 __global__ void __launch_bounds__(NT)
 gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
             int k, double zero_tol, double eps_default, int det_only,
@@ -295,7 +297,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 #pragma unroll
     for (int c = 0; c < kNch; ++c) {
         const int j0 = c * tpr * VE + tc * VE;
-        if (c < nch) {   // the same for the whole workgroup: a scalar branch
+        if (FULL || c < nch) {   // the same for the whole workgroup: a scalar branch
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
                 const int j = j0 + e;
@@ -398,14 +400,14 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 // would serialise them
 #pragma unroll
                 for (int c = 0; c < kNch; ++c)
-                    if (c < nch)
+                    if (FULL || c < nch)
 #pragma unroll
                         for (int e = 0; e < VE; ++e)
                             vset<VT, T>(wb[g][c], e,
                                         update(vget<VT, T>(wb[g][c], e), c, e, c * tpr * VE + tc * VE + e));
 #pragma unroll
                 for (int c = 0; c < kNch; ++c)
-                    if (c < nch) row_st(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
+                    if (FULL || c < nch) row_st(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
             } else {
 #pragma unroll
                 for (int c = 0; c < kNch; ++c) {
@@ -528,7 +530,7 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int NT, bool NTL>
+template <typename T, int NT, bool NTL, bool FULL>
 static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDesc &single,
                             const int *grid_per_step,
                             int grid_init, int grid_finish, int max_n, int gather_grid,
@@ -542,7 +544,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         if (e != hipSuccess) return e;
     }
     for (int k = 0; k < max_n; ++k) {
-        hipLaunchKernelGGL((gj_big_step<T, NT, NTL>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
+        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
                            dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only,
                            run_flag);
         e = hipGetLastError();
@@ -562,17 +564,18 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
     return e;
 }
 
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, const BigDesc *descs, const int2 *bmap,
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, const BigDesc *descs,
+                      const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
                       void *const *events, const int32_t *run_flag, hipStream_t s) {
-#define GJ_BIG_CASE(TT, NTV)                                                                    \
-    return nt_loads ? run_big_t<TT, NTV, true>(descs, bmap, single, grid_per_step, grid_init,      \
-                                               grid_finish, max_n, gather_grid, zero_tol,          \
-                                               eps_default, det_only, events, run_flag, s)         \
-                    : run_big_t<TT, NTV, false>(descs, bmap, single, grid_per_step, grid_init,     \
-                                                grid_finish, max_n, gather_grid, zero_tol,         \
-                                                eps_default, det_only, events, run_flag, s)
+#define GJ_BIG_ARGS descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n, gather_grid, \
+                    zero_tol, eps_default, det_only, events, run_flag, s
+#define GJ_BIG_CASE(TT, NTV)                                                               \
+    return nt_loads ? (full ? run_big_t<TT, NTV, true, true>(GJ_BIG_ARGS)                  \
+                            : run_big_t<TT, NTV, true, false>(GJ_BIG_ARGS))                \
+                    : (full ? run_big_t<TT, NTV, false, true>(GJ_BIG_ARGS)                 \
+                            : run_big_t<TT, NTV, false, false>(GJ_BIG_ARGS))
     if (fp32) {
         switch (nt) {
             case 256: GJ_BIG_CASE(float, 256);
@@ -587,6 +590,7 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, const BigDesc *descs, co
         }
     }
 #undef GJ_BIG_CASE
+#undef GJ_BIG_ARGS
     return hipErrorInvalidValue;
 }
 

@@ -27,7 +27,8 @@ hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks
                          double eps_default, int det_only, const int32_t *run_flag,
                          hipStream_t s);
 
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, const BigDesc *descs, const int2 *bmap,
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, const BigDesc *descs,
+                      const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init,
                       int grid_finish, int max_n, int gather_grid, double zero_tol,
                       double eps_default, int det_only, void *const *events,
