@@ -91,6 +91,19 @@ def test_streaming_sizes(gj, n):
     _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n}")
 
 
+@pytest.mark.parametrize("n,nt,rows", [(300, 1, 0), (777, 1, 0), (1000, 1, 3), (1000, 0, 64),
+                                         (1025, 1, 0), (2049, 0, 0)])
+def test_streaming_variants(gj, n, nt, rows, monkeypatch):
+    """The step kernel's instantiations: nontemporal row loads (chosen by the
+    library only past the Infinity Cache, forced here), full or partial
+    register chunks, and rows per workgroup away from the tuned value."""
+    monkeypatch.setenv("GJ_BIG_NT", str(nt))
+    if rows:
+        monkeypatch.setenv("GJ_BIG_ROWS", str(rows))
+    A = inputs.rng_for(0, 3100 + n).standard_normal((n, n))
+    _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n} nt={nt} rows={rows}")
+
+
 @pytest.mark.parametrize("n", [4, 16, 64, 128, 256, 512])
 def test_hadamard_ties(gj, n):
     """Every candidate ties at every step: the tie-break on the swapped
