@@ -64,21 +64,72 @@ constexpr int kNch = 8;  // column chunks per thread: n <= kNch * V * threads-pe
 template <int NT> constexpr bool kEarlyRows = NT < 1024;
 template <int NT> constexpr int kRowGroup = kEarlyRows<NT> ? 2 : 1;
 
+// Wavefront argmax of (a, v, key, pos) candidates without LDS: DPP moves
+// within rows of 16 lanes, then permlane swaps across rows (gfx950).  pos
+// packs the physical position (row << 16 | column, 0xFFFF for -1).
+struct BigCand {
+    double a, v;
+    uint32_t key, pos;
+};
+__device__ __forceinline__ void bigcand_take(BigCand &c, const BigCand &o) {
+    if (better(o.a, o.key, c.a, c.key)) c = o;
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const uint32_t lo = dpp_u32<CTRL>((uint32_t)__double2loint(x));
+    const uint32_t hi = dpp_u32<CTRL>((uint32_t)__double2hiint(x));
+    return __hiloint2double((int)hi, (int)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ void bigcand_dpp(BigCand &c) {
+    BigCand o;
+    o.a = dpp_f64<CTRL>(c.a);
+    o.v = dpp_f64<CTRL>(c.v);
+    o.key = dpp_u32<CTRL>(c.key);
+    o.pos = dpp_u32<CTRL>(c.pos);
+    bigcand_take(c, o);
+}
+// permlane{16,32}_swap leave the pair in the same order in both lanes, so
+// combining the two halves gives both lanes the same winner
+template <bool P32>
+__device__ __forceinline__ void bigcand_perm(BigCand &c) {
+    uint32_t w[6] = {(uint32_t)__double2loint(c.a), (uint32_t)__double2hiint(c.a),
+                     (uint32_t)__double2loint(c.v), (uint32_t)__double2hiint(c.v), c.key, c.pos};
+    uint32_t x[6], y[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        auto pr = P32 ? __builtin_amdgcn_permlane32_swap(w[e], w[e], false, false)
+                      : __builtin_amdgcn_permlane16_swap(w[e], w[e], false, false);
+        x[e] = pr[0];
+        y[e] = pr[1];
+    }
+    BigCand cx, cy;
+    cx.a = __hiloint2double((int)x[1], (int)x[0]); cx.v = __hiloint2double((int)x[3], (int)x[2]);
+    cx.key = x[4]; cx.pos = x[5];
+    cy.a = __hiloint2double((int)y[1], (int)y[0]); cy.v = __hiloint2double((int)y[3], (int)y[2]);
+    cy.key = y[4]; cy.pos = y[5];
+    bigcand_take(cx, cy);
+    c = cx;
+}
+
 // Workgroup-wide argmax of BigPart-like candidates, keyed on the logical
 // position.  Result broadcast to every thread.
 template <int NT>
 __device__ inline void block_argmax(double &a, double &v, uint32_t &key, int &ip, int &jp,
                                     double *s_a, double *s_v, uint32_t *s_k, int *s_i, int *s_j) {
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-#pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) {
-        double oa = __shfl_xor(a, off, kWave);
-        double ov = __shfl_xor(v, off, kWave);
-        uint32_t ok = (uint32_t)__shfl_xor((int)key, off, kWave);
-        int oi = __shfl_xor(ip, off, kWave);
-        int oj = __shfl_xor(jp, off, kWave);
-        if (better(oa, ok, a, key)) { a = oa; v = ov; key = ok; ip = oi; jp = oj; }
-    }
+    BigCand c;
+    c.a = a; c.v = v; c.key = key;
+    c.pos = ((uint32_t)(ip & 0xFFFF) << 16) | (uint32_t)(jp & 0xFFFF);
+    bigcand_dpp<0xB1>(c);    // quad_perm [1,0,3,2]
+    bigcand_dpp<0x4E>(c);    // quad_perm [2,3,0,1]
+    bigcand_dpp<0x141>(c);   // row_half_mirror
+    bigcand_dpp<0x140>(c);   // row_mirror
+    bigcand_perm<false>(c);
+    bigcand_perm<true>(c);
+    a = c.a; v = c.v; key = c.key;
+    ip = (c.pos >> 16) == 0xFFFFu ? -1 : (int)(c.pos >> 16);
+    jp = (c.pos & 0xFFFFu) == 0xFFFFu ? -1 : (int)(c.pos & 0xFFFFu);
     constexpr int NW = NT / kWave;
     if constexpr (NW > 1) {
         if (lane == 0) { s_a[w] = a; s_v[w] = v; s_k[w] = key; s_i[w] = ip; s_j[w] = jp; }
