@@ -384,7 +384,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     __syncthreads();
 
     // ---- 4. eq. 15 on the owned rows + fused pivot search for step k+1
-    double ba = 0.0, bv = 0.0;   // "no candidate": (0, key 0xFFFFFFFF)
+    T bvT = (T)0;                 // running best (signed), "no candidate": (0, key 0xFFFFFFFF)
     uint32_t bk = 0xFFFFFFFFu;
     int bi = -1, bj = -1;
     bool nf = false;
@@ -423,12 +423,11 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 const T nv = Num<T>::fma_(-q, prow[c][e], cur);
                 const int cl = ckey[c][e];
                 const bool cand = rcand & (cl > k);   // '&', '|': no short-circuit branches
-                const double an = fabs((double)nv);
-                nf |= cand & !(an <= 1.7976931348623157e308);
+                const T an = Num<T>::abs_(nv), ab = Num<T>::abs_(bvT);   // in T: exact
+                nf |= cand & !Num<T>::finite_(an);
                 const uint32_t key = rkey | (uint32_t)cl;
-                const bool upd = cand & ((an > ba) | ((an == ba) & (key < bk)));
-                ba = upd ? an : ba;
-                bv = upd ? (double)nv : bv;
+                const bool upd = cand & ((an > ab) | ((an == ab) & (key < bk)));
+                bvT = upd ? nv : bvT;
                 bk = upd ? key : bk;
                 bi = upd ? i : bi;
                 bj = upd ? j : bj;
@@ -481,6 +480,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     }
     if (k + 1 < n) {
         const int any_nf = __syncthreads_or(nf ? 1 : 0);
+        double bv = (double)bvT, ba = fabs(bv);
         block_argmax<NT>(ba, bv, bk, bi, bj, s_a, s_v, s_k, s_i, s_j);
         if (t == 0) {
             BigPart o;
