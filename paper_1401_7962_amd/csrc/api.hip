@@ -61,10 +61,14 @@ namespace {
 
 // ------------------------------------------------------------ tuning table
 // Written by the project's autotuner (paper_1401_7962_amd/tune.py) as lines
-//     big_rows <f32|f64> <n_min> <n_max> <rows per workgroup>
+//     big_rows <f32|f64> <n_min> <n_max> <rows per workgroup> [<counted %>]
 // and read once from $GJ_TUNE_FILE, else from gj_tune.txt beside libgj.so.
-// $GJ_BIG_ROWS, when set, overrides it (the autotuner uses that to sweep).
-struct TuneEntry { int fp32, nmin, nmax, rows; };
+// The optional last field is the share of a step's work units handed out by
+// the step kernel's counter (default 0: every unit taken by index).
+// $GJ_BIG_ROWS and $GJ_BIG_COUNTED, when set, override the two fields (the
+// autotuner uses them to sweep); $GJ_BIG_STATIC sets the units taken by
+// index per workgroup directly.
+struct TuneEntry { int fp32, nmin, nmax, rows, counted; };
 std::vector<TuneEntry> g_tune;
 std::once_flag g_tune_once;
 
@@ -85,24 +89,28 @@ void load_tune_table() {
     char line[256];
     while (std::fgets(line, sizeof(line), fp)) {
         char key[64], prec[16];
-        int lo, hi, v;
-        if (std::sscanf(line, "%63s %15s %d %d %d", key, prec, &lo, &hi, &v) == 5 &&
-            std::strcmp(key, "big_rows") == 0 && v >= 1 && v <= 64 && lo <= hi)
-            g_tune.push_back(TuneEntry{std::strcmp(prec, "f32") == 0 ? 1 : 0, lo, hi, v});
+        int lo, hi, v, pct = 0;
+        const int got = std::sscanf(line, "%63s %15s %d %d %d %d", key, prec, &lo, &hi, &v, &pct);
+        if (got >= 5 && std::strcmp(key, "big_rows") == 0 && v >= 1 && v <= 64 && lo <= hi) {
+            if (got < 6 || pct < 0 || pct > 90) pct = 0;
+            g_tune.push_back(TuneEntry{std::strcmp(prec, "f32") == 0 ? 1 : 0, lo, hi, v, pct});
+        }
     }
     std::fclose(fp);
 }
 
-int tuned_rows(bool fp32, int n) {
+const TuneEntry *tuned(bool fp32, int n) {
     std::call_once(g_tune_once, load_tune_table);
     for (const TuneEntry &e : g_tune)
-        if (e.fp32 == (fp32 ? 1 : 0) && n >= e.nmin && n <= e.nmax) return e.rows;
-    return 0;
+        if (e.fp32 == (fp32 ? 1 : 0) && n >= e.nmin && n <= e.nmax) return &e;
+    return nullptr;
 }
 
 // ------------------------------------------------------ streaming-path plan
 struct BigShape {
     int n, nt, tpr, R, nblk;
+    int nunits, share;   // work units of a step; units per workgroup
+    int ustat;           // units per workgroup taken by index (the rest by counter)
     int64_t ldw;
 };
 
@@ -128,13 +136,31 @@ BigShape big_shape(int n, bool fp32, int nt) {
     if (tpr > nt) tpr = nt;
     s.tpr = tpr;
     const int rg = nt / tpr;
+    const TuneEntry *te = tuned(fp32, n);
     int R = env_int("GJ_BIG_ROWS", 0);
-    if (R <= 0) R = tuned_rows(fp32, n);
+    if (R <= 0 && te) R = te->rows;
     if (R <= 0) R = std::max(1, n / 512);
-    R = std::max(R, rg);
-    R = std::min(R, 64);
+    // a work unit of the step kernel is one register group (2 rows per
+    // thread below 1024 threads, else 1), or the workgroup's rows if fewer;
+    // a workgroup covers whole units.  All are powers of two, so R stays
+    // <= 64 rows: the kernel's LDS tables.
+    R = std::max(std::min(R, 64), rg);
+    const int unit = std::min((nt < 1024 ? 2 : 1) * rg, R);
+    R = (R + unit - 1) / unit * unit;
     s.R = R;
     s.nblk = (n + R - 1) / R;
+    s.nunits = (n + unit - 1) / unit;
+    s.share = R / unit;
+    // units taken by index per workgroup: all of its share, less the tuned
+    // share left to the counter (GJ_BIG_STATIC overrides); the counter is
+    // compiled only into the full-chunk kernels below 1024 threads
+    const int per = tpr * (fp32 ? 4 : 2);
+    const bool cnt_ok = (n + per - 1) / per == 8 && nt < 1024;
+    int pct = env_int("GJ_BIG_COUNTED", -1);
+    if (pct < 0 || pct > 90) pct = te ? te->counted : 0;
+    int S = env_int("GJ_BIG_STATIC", 0);
+    if (S <= 0) S = s.share - (s.share * pct + 50) / 100;
+    s.ustat = cnt_ok ? std::max(1, std::min(S, s.share)) : s.share;
     const int64_t chunk = (int64_t)tpr * ve;
     s.ldw = ((int64_t)n + chunk - 1) / chunk * chunk + env_int("GJ_BIG_PAD", 0) * ve;
     return s;
@@ -149,6 +175,10 @@ bool big_nt_loads(size_t swept_bytes) {
 }
 size_t big_swept_bytes(const BigShape &s, bool fp32) {
     return (size_t)s.n * (size_t)s.ldw * (fp32 ? 4 : 8);
+}
+// Some work units of a step are handed out by the step kernel's counter.
+bool big_counted(const BigShape &s) {
+    return (int64_t)s.nblk * s.ustat < s.nunits;
 }
 // Every thread of the row uses all 8 of its vector chunks (the step kernel
 // then compiles without the per-chunk tests).
@@ -203,6 +233,7 @@ BigDesc make_desc(const BigShape &s, const BigBufs &b, char *ws, const double *A
     d.R = s.R;
     d.nblk = s.nblk;
     d.tpr = s.tpr;
+    d.ustat = s.ustat;
     return d;
 }
 
@@ -219,6 +250,7 @@ struct BatchPlan {
     int big_nt = 256, big_max_n = 0;
     size_t big_swept = 0;          // bytes of W swept per step (all streaming members)
     bool big_full = true;          // every streaming member uses all chunks
+    bool big_counted = false;      // some member leaves units to the counter
     int cls_start[kOnchipClasses] = {0}, cls_count[kOnchipClasses] = {0};
     // byte offsets in the workspace
     size_t off_mats = 0, off_tasks = 0, off_queue = 0, off_descs = 0, off_bmap = 0, total = 0;
@@ -270,6 +302,11 @@ bool plan_batch(int batch, const int32_t *n_host, bool fp32, BatchPlan &P) {
             P.big_swept += big_swept_bytes(s, fp32);
             P.big_full = P.big_full && big_full(s, fp32);
             nb += s.nblk;
+        }
+        // one launch serves every member: the counter only if all are full
+        for (BigShape &s : P.big_shapes) {
+            if (!P.big_full) s.ustat = s.share;
+            P.big_counted = P.big_counted || big_counted(s);
         }
         P.off_bmap = c; c = a256(c + sizeof(int2) * nb);
         for (size_t x = 0; x < P.big_members.size(); ++x) {
@@ -354,7 +391,7 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
     BigBufs bb = big_bufs(sh, fp32, 0);
     if (ws_bytes < bb.end) return GJ_E_WORKSPACE;
     BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
-    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32),
+    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32), big_counted(sh),
                               nullptr, nullptr,
                               d, nullptr, sh.nblk, sh.nblk, n,
                               det_only ? 0 : sh.nblk, o.zero_tol, eps_default, det_only ? 1 : 0,
@@ -445,7 +482,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, true, nt);
         BigBufs bb = big_bufs(sh, true, L.big32);
         d32 = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true),
+        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true), big_counted(sh),
                           nullptr, nullptr, d32,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, 0.0, 0.0, det_only ? 1 : 0, o.events, nullptr, s));
@@ -509,7 +546,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, false, nt);
         BigBufs bb = big_bufs(sh, false, L.over64);
         BigDesc d = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false),
+        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false), big_counted(sh),
                           nullptr, nullptr, d,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
@@ -646,6 +683,7 @@ struct RefBatchPlan {
     int fb_nt = 256;
     size_t fb_swept = 0;
     bool fb_full = true;
+    bool fb_counted = false;
     size_t off_fb_descs = 0, off_fb_bmap = 0;
     // Newton-Schulz product lists
     GemmList r0, upd[2], res[2];
@@ -704,6 +742,10 @@ bool plan_refined_batch(int batch, const int32_t *n_host, RefBatchPlan &P) {
             P.fb_full = P.fb_full && big_full(s, false);
             P.fb_bufs.push_back(big_bufs(s, false, P.region[m]));
             nb += s.nblk;
+        }
+        for (BigShape &s : P.fb_shapes) {
+            if (!P.fb_full) s.ustat = s.share;
+            P.fb_counted = P.fb_counted || big_counted(s);
         }
         P.off_fb_bmap = c; c = a256(c + sizeof(int2) * nb);
         for (size_t x = 0; x < P.e32.big_members.size(); ++x)
@@ -963,7 +1005,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)E.bmap.size();
-        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full,
+        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full, E.big_counted,
                           reinterpret_cast<const BigDesc *>(w + E.off_descs),
                           reinterpret_cast<const int2 *>(w + E.off_bmap), BigDesc(),
                           E.grid_per_step.data(), nb, nb, E.big_max_n, nb, 0.0, 0.0, 0, o.events,
@@ -990,7 +1032,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)P.fb_bmap.size();
-        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full,
+        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full, P.fb_counted,
                           reinterpret_cast<const BigDesc *>(w + P.off_fb_descs),
                           reinterpret_cast<const int2 *>(w + P.off_fb_bmap), BigDesc(),
                           P.fb_grid.data(), nb, nb, E.big_max_n, nb, o.zero_tol, kEps64, 0, nullptr,
@@ -1251,7 +1293,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         }
         if (!P.big_members.empty()) {
             const int nb = (int)P.bmap.size();
-            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full,
+            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full, P.big_counted,
                                       reinterpret_cast<const BigDesc *>(w + P.off_descs),
                                       reinterpret_cast<const int2 *>(w + P.off_bmap), BigDesc(),
                                       P.grid_per_step.data(), nb, nb, P.big_max_n, nb, o.zero_tol,

@@ -5,8 +5,13 @@
 // HBM and back, so the sweep is HBM-bound (16 n^2 bytes per FP64 step).
 //
 // Layout and ownership
-//   * Each workgroup owns R whole rows of W.  It reads only its own rows, the
-//     pivot row and O(n) bookkeeping, and writes only its own rows.
+//   * A step sweeps W in work units of whole rows (as many rows as a
+//     workgroup holds in registers at once).  Each workgroup takes a few
+//     units by its index, then asks a per-step counter for more until none
+//     are left: on MI355X some XCDs stream measurably slower than others, and
+//     a fixed split would make every step wait for the slowest.  A unit is
+//     read and written only by the workgroup that took it; besides it, a
+//     workgroup reads the pivot row and O(n) bookkeeping.
 //   * Row and column swaps (Obs. 2-3) are virtual: rows and columns stay where
 //     they are and two index maps (physical -> logical position, double
 //     buffered by step parity) record the permutation.  Ties in the pivot
@@ -14,9 +19,11 @@
 //     logical indices, i.e. on the positions in the swapped matrix.
 //   * The pivot row is divided by the pivot (eq. 14) lazily: during step k every
 //     workgroup reads the unscaled pivot row and divides it itself, and the
-//     owner writes the scaled values one step later while applying step k+1.
-//     No workgroup ever reads a row that another one is writing.
-//   * The multiplier a_ik of eq. 15 comes from the workgroup's own row.
+//     workgroup that sweeps it at step k+1 writes the scaled values while
+//     applying that step.  No workgroup ever reads a row that another one is
+//     writing.
+//   * The multiplier a_ik of eq. 15 is read from the row before the sweep of
+//     its unit starts (the sweep overwrites it).
 //   * The pivot search of step k+1 is fused into the sweep of step k: each
 //     workgroup leaves one candidate (|a|, logical row, logical column,
 //     physical row, physical column); every workgroup of step k+1 reduces the
@@ -63,6 +70,8 @@ constexpr int kNch = 8;  // column chunks per thread: n <= kNch * V * threads-pe
 // each chunk where it is used.
 template <int NT> constexpr bool kEarlyRows = NT < 1024;
 template <int NT> constexpr int kRowGroup = kEarlyRows<NT> ? 2 : 1;
+// Rows per workgroup of the step kernel (its own units) are at most this many.
+constexpr int kMaxUnit = 64;
 
 // Wavefront argmax of (a, v, key, pos) candidates without LDS: DPP moves
 // within rows of 16 lanes, then permlane swaps across rows (gfx950).  pos
@@ -163,7 +172,10 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const int tpr = d.tpr, rsub = t / tpr, tc = t % tpr, rg = NT / tpr;
     T *W = reinterpret_cast<T *>(d.W);
     const int r0 = rb * d.R, r1 = min(n, r0 + d.R);
-    if (rb == 0 && t == 0) { d.hdr->status = 0; d.hdr->rank = n; d.hdr->tau = 0.0; }
+    if (rb == 0 && t == 0) {
+        d.hdr->status = 0; d.hdr->rank = n; d.hdr->tau = 0.0;
+        d.hdr->ticket[0] = 0; d.hdr->ticket[1] = 0;
+    }
     if (rb == 0)
         for (int j = t; j < n; j += NT) d.collog[j] = j;
     double ba = 0.0, bv = 0.0;   // "no candidate": (0, key 0xFFFFFFFF)
@@ -201,7 +213,9 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 // ------------------------------------------------------------------ step
 // FULL: every matrix of the launch uses all kNch chunks per thread (the
 // chunk tests then fold away; they cost about 8% at n = 4096).
-template <typename T, int NT, bool NTL, bool FULL>
+// CNT: some units may come from the per-step counter.  Without it each
+// workgroup sweeps only its own rows, with no barrier in the sweep.
+template <typename T, int NT, bool NTL, bool FULL, bool CNT>
 __global__ void __launch_bounds__(NT)
 gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
             int k, double zero_tol, double eps_default, int det_only,
@@ -214,8 +228,9 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     __shared__ double s_a[NT / kWave], s_v[NT / kWave];
     __shared__ uint32_t s_k[NT / kWave];
     __shared__ int s_i[NT / kWave], s_j[NT / kWave];
-    __shared__ T s_q[64];
-    __shared__ int s_rl[64];
+    __shared__ T s_qs[kMaxUnit], s_qd[2][kMaxUnit];   // multipliers: own rows, counted units
+    __shared__ int s_rls[kMaxUnit], s_rld[2][kMaxUnit];  // new logical row indices (-1: skip)
+    __shared__ int s_nx[2], s_first;
 
     const int2 bm = descs ? bmap[blockIdx.x] : make_int2(0, (int)blockIdx.x);
     const BigDesc d = descs ? descs[bm.x] : single;
@@ -226,7 +241,6 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const int tpr = d.tpr, rsub = t / tpr, tc = t % tpr, rg = NT / tpr;
     const gptr<T> W = glb(reinterpret_cast<T *>(d.W));
     const int64_t ldw = d.ldw;
-    const int r0 = rb * d.R, r1 = min(n, r0 + d.R), nrows = r1 - r0;
     const int nch = (n + tpr * VE - 1) / (tpr * VE);
     const gptr<BigHdr> hdr = glb(d.hdr);
     const gptr<const int32_t> rl_old = glb(static_cast<const int32_t *>(d.rowlog)) + (size_t)(k & 1) * d.mstride;
@@ -248,7 +262,20 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     if (k > 0) prev = glb(d.steps)[k - 1];
     const gptr<const BigPart> P = glb(static_cast<const BigPart *>(d.part)) + (size_t)(k & 1) * d.nblk;
     const BigPart c0 = P[min(t, d.nblk - 1)];
-    const int ro_own = rl_old[r0 + min(t, nrows - 1)];   // old logical index of owned row t
+    // Work units: one register group of rows (B * rg rows).  Units
+    // [rb*S, rb*S+S) are this workgroup's; when the workgroups' units do not
+    // cover the matrix, the rest are handed out by a per-step counter.
+    constexpr int B = kRowGroup<NT>;
+    const int U = min(B * rg, d.R);                // rows per unit; slots x >= U are unused
+    const int nunits = (n + U - 1) / U;
+    const int S = d.ustat;                         // S * U <= R <= kMaxUnit
+    const int s0 = rb * S;
+    const int nstat = max(0, min(S, nunits - s0));
+    const int r0 = s0 * U;                         // the workgroup's own rows: [r0, r0 + nsr)
+    const int nsr = nstat > 0 ? min(nstat * U, n - r0) : 0;
+    const int dyn0 = d.nblk * S;                   // first unit of the counter
+    const bool dyn = CNT && dyn0 < nunits;         // (then every workgroup has S units)
+    const int ro_own = rl_old[nsr > 0 ? r0 + min(t, nsr - 1) : 0];   // old logical index of own row t
     VI co[kNch];
 #pragma unroll
     for (int c = 0; c < kNch; ++c)   // in bounds: the maps hold ldw >= nch * tpr * VE entries
@@ -293,26 +320,25 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const int rp = pi, cp = pj;
     const T p = (T)pv;
 
-    // ---- 2. the winner's row and the owned rows' multipliers (eq. 15),
-    //         then the first group of owned rows (they do not depend on the
-    //         winner; requested after it so that they do not delay it)
+    // ---- 2. the winner's row, the own rows' multipliers (eq. 15), then the
+    //         first group of own rows
     const gptr<const T> Wp = W + (int64_t)rp * ldw;
     VT pw[kNch];
 #pragma unroll
     for (int c = 0; c < kNch; ++c)
         pw[c] = *reinterpret_cast<gptr<const VT>>(Wp + (c < nch ? c : 0) * tpr * VE + tc * VE);
-    T q_own = W[(int64_t)(r0 + min(t, nrows - 1)) * ldw + cp];
-    constexpr int B = kRowGroup<NT>;
+    // (slots without a row read the pivot row, which nobody writes this step)
+    T q_own = W[(int64_t)(nsr > 0 ? r0 + min(t, nsr - 1) : rp) * ldw + cp];
     VT wb[B][kNch];
     const bool early = kEarlyRows<NT> && !det_only;
     if constexpr (kEarlyRows<NT>) {
         // rows not owned, the pivot row (written at step k+1) and every row
-        // in det_only mode read row r0 instead, and are not used
+        // in det_only mode read the pivot row instead, and are not used
 #pragma unroll
         for (int g = 0; g < B; ++g) {
             const int x = rsub + g * rg;
-            const bool use = early && x < nrows && r0 + x != rp;
-            const gptr<const T> Wi = W + (int64_t)(use ? r0 + x : r0) * ldw;
+            const bool use = early && x < min(U, nsr) && r0 + x != rp;
+            const gptr<const T> Wi = W + (int64_t)(use ? r0 + x : rp) * ldw;
 #pragma unroll
             for (int c = 0; c < kNch; ++c)
                 wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + (c < nch ? c : 0) * tpr * VE + tc * VE));
@@ -322,23 +348,24 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
         StepRec s;
         s.p = pv; s.rphys = rp; s.cphys = cp; s.rlog = rlog; s.clog = clog;
         glb(d.steps)[k] = s;
+        __hip_atomic_store(&hdr->ticket[(k + 1) & 1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     const int rpp = prev.rphys, cpp = prev.cphys;
     const T pp = (T)prev.p;
     const T y = Num<T>::one() / p, yp = Num<T>::one() / pp;   // RN(1/p): div_pivot seeds
     const bool p_ok = div_pivot_ok(p), pp_ok = div_pivot_ok(pp);
 
-    // multipliers and new logical row indices of the owned rows
-    if (t < nrows) {
-        const int i = r0 + t;
-        T q = q_own;
-        if (i == rpp) q = div_pivot(q, pp, yp, pp_ok);   // deferred eq. 14 of the previous step
-        s_q[t] = q;
-        const int ro = ro_own;
+    // multiplier (with the previous pivot row's deferred eq. 14) and new
+    // logical index of row i, whose old logical index is ro
+    auto row_meta = [&](int i, T qraw, int ro, T *sq, int *srl, int x) {
+        T q = qraw;
+        if (i == rpp) q = div_pivot(q, pp, yp, pp_ok);
         const int rn = (i == rp) ? k : ((ro == k) ? rlog : ro);
-        s_rl[t] = (det_only && ro < k) ? -1 : rn;   // -1: row not needed
+        sq[x] = q;
+        srl[x] = (det_only && ro < k) ? -1 : rn;   // -1: row not needed
         rl_new[i] = rn;
-    }
+    };
+    if (t < nsr) row_meta(r0 + t, q_own, ro_own, s_qs, s_rls, t);
 
     // ---- 3. the pivot row divided by the pivot (eq. 14) and the new logical
     //         column indices, for this thread's columns
@@ -355,8 +382,8 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 const int o = vget<VI, int>(co[c], e);
                 const int cn = (j == cp) ? k : ((o == k) ? clog : o);
                 ckey[c][e] = (j < n) ? cn : -1;
-                const T qv = div_pivot_fast(vget<VT, T>(pw[c], e), p, y, p_ok, slow);
-                prow[c][e] = (j == cp) ? y : qv;
+                const T qd = div_pivot_fast(vget<VT, T>(pw[c], e), p, y, p_ok, slow);
+                prow[c][e] = (j == cp) ? y : qd;
             }
         } else {
 #pragma unroll
@@ -383,100 +410,180 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     }
     __syncthreads();
 
-    // ---- 4. eq. 15 on the owned rows + fused pivot search for step k+1
+    // ---- 4. eq. 15 on the swept rows + fused pivot search for step k+1
     T bvT = (T)0;                 // running best (signed), "no candidate": (0, key 0xFFFFFFFF)
     uint32_t bk = 0xFFFFFFFFu;
     int bi = -1, bj = -1;
     bool nf = false;
-    // later groups (and the first one in det_only mode): rows that are not
-    // needed are not requested
-    auto load_group = [&](int xg) {
-#pragma unroll
-        for (int g = 0; g < B; ++g) {
-            const int x = xg + g * rg;
-            if (x < nrows && s_rl[x] >= 0 && r0 + x != rp) {
-                const gptr<const T> Wi = W + (int64_t)(r0 + x) * ldw;
+    // one row already in wb[g] (or, with 1024 threads, read chunk by chunk)
+    auto sweep_row = [&](int g, int i, T q, int rn) {
+        const bool fix = (i == rpp);
+        const bool rcand = rn > k;
+        const uint32_t rkey = (uint32_t)rn << 16;
+        const gptr<T> Wi = W + (int64_t)i * ldw;
+        // eq. 15 for one element, then the branch-free candidate update
+        // (nearly every lane takes part, so selects beat branches)
+        auto update = [&](T cur, int c, int e, int j) -> T {
+            cur = (j == cp) ? (T)0 : cur;
+            const T nv = Num<T>::fma_(-q, prow[c][e], cur);
+            const int cl = ckey[c][e];
+            const bool cand = rcand & (cl > k);   // '&', '|': no short-circuit branches
+            const T an = Num<T>::abs_(nv), ab = Num<T>::abs_(bvT);   // in T: exact
+            nf |= cand & !Num<T>::finite_(an);
+            const uint32_t key = rkey | (uint32_t)cl;
+            const bool upd = cand & ((an > ab) | ((an == ab) & (key < bk)));
+            bvT = upd ? nv : bvT;
+            bk = upd ? key : bk;
+            bi = upd ? i : bi;
+            bj = upd ? j : bj;
+            return nv;
+        };
+        if constexpr (kEarlyRows<NT>) {
+            if (fix) {   // the previous pivot row: its deferred eq. 14 first
 #pragma unroll
                 for (int c = 0; c < kNch; ++c)
-                    if (c < nch) wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + c * tpr * VE + tc * VE));
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) {
+                        const int j = c * tpr * VE + tc * VE + e;
+                        const T cur = vget<VT, T>(wb[g][c], e);
+                        vset<VT, T>(wb[g][c], e, (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok));
+                    }
+            }
+            // the whole row is updated in place in wb before any of it is
+            // stored: a store's data registers cannot be reused until the
+            // store has completed, so a register shared by all chunks would
+            // serialise them
+#pragma unroll
+            for (int c = 0; c < kNch; ++c)
+                if (FULL || c < nch)
+#pragma unroll
+                    for (int e = 0; e < VE; ++e)
+                        vset<VT, T>(wb[g][c], e,
+                                    update(vget<VT, T>(wb[g][c], e), c, e, c * tpr * VE + tc * VE + e));
+#pragma unroll
+            for (int c = 0; c < kNch; ++c)
+                if (FULL || c < nch) row_st(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < kNch; ++c) {
+                if (c < nch) {
+                    const int j0 = c * tpr * VE + tc * VE;
+                    VT w = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + j0));
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) {
+                        const int j = j0 + e;
+                        T cur = vget<VT, T>(w, e);
+                        if (fix) cur = (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok);
+                        vset<VT, T>(w, e, update(cur, c, e, j));
+                    }
+                    row_st(reinterpret_cast<gptr<VT>>(Wi + j0), w);
+                }
             }
         }
     };
-    if (kEarlyRows<NT> && !early) load_group(rsub);
-    for (int xg = rsub; xg < nrows; xg += B * rg) {
+    // rows of a unit into wb: every slot, so that the memory counters stay
+    // exact (slots without a row read the pivot row); in det_only mode only
+    // the rows still needed, after the barrier that says which they are
+    auto load_rows = [&](int i0, int nr, const int *srl, bool all) {
 #pragma unroll
         for (int g = 0; g < B; ++g) {
-            const int x = xg + g * rg;
-            if (x >= nrows) continue;
-            const int i = r0 + x;
-            const int rn = s_rl[x];
-            if (i == rp || rn < 0) continue;   // pivot row: written at step k+1
-            const T q = s_q[x];
-            const bool fix = (i == rpp);
-            const bool rcand = rn > k;
-            const uint32_t rkey = (uint32_t)rn << 16;
-            const gptr<T> Wi = W + (int64_t)i * ldw;
-            // eq. 15 for one element, then the branch-free candidate update
-            // (nearly every lane takes part, so selects beat branches)
-            auto update = [&](T cur, int c, int e, int j) -> T {
-                cur = (j == cp) ? (T)0 : cur;
-                const T nv = Num<T>::fma_(-q, prow[c][e], cur);
-                const int cl = ckey[c][e];
-                const bool cand = rcand & (cl > k);   // '&', '|': no short-circuit branches
-                const T an = Num<T>::abs_(nv), ab = Num<T>::abs_(bvT);   // in T: exact
-                nf |= cand & !Num<T>::finite_(an);
-                const uint32_t key = rkey | (uint32_t)cl;
-                const bool upd = cand & ((an > ab) | ((an == ab) & (key < bk)));
-                bvT = upd ? nv : bvT;
-                bk = upd ? key : bk;
-                bi = upd ? i : bi;
-                bj = upd ? j : bj;
-                return nv;
-            };
-            if constexpr (kEarlyRows<NT>) {
-                if (fix) {   // the previous pivot row: its deferred eq. 14 first
-#pragma unroll
-                    for (int c = 0; c < kNch; ++c)
-#pragma unroll
-                        for (int e = 0; e < VE; ++e) {
-                            const int j = c * tpr * VE + tc * VE + e;
-                            const T cur = vget<VT, T>(wb[g][c], e);
-                            vset<VT, T>(wb[g][c], e, (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok));
-                        }
-                }
-                // the whole row is updated in place in wb before any of it is
-                // stored: a store's data registers cannot be reused until the
-                // store has completed, so a register shared by all chunks
-                // would serialise them
+            const int x = rsub + g * rg, i = i0 + x;
+            const bool use = x < nr && i != rp;
+            if (all || (use && srl[x] >= 0)) {
+                const gptr<const T> Wi = W + (int64_t)(use ? i : rp) * ldw;
 #pragma unroll
                 for (int c = 0; c < kNch; ++c)
-                    if (FULL || c < nch)
-#pragma unroll
-                        for (int e = 0; e < VE; ++e)
-                            vset<VT, T>(wb[g][c], e,
-                                        update(vget<VT, T>(wb[g][c], e), c, e, c * tpr * VE + tc * VE + e));
-#pragma unroll
-                for (int c = 0; c < kNch; ++c)
-                    if (FULL || c < nch) row_st(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
-            } else {
-#pragma unroll
-                for (int c = 0; c < kNch; ++c) {
-                    if (c < nch) {
-                        const int j0 = c * tpr * VE + tc * VE;
-                        VT w = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + j0));
-#pragma unroll
-                        for (int e = 0; e < VE; ++e) {
-                            const int j = j0 + e;
-                            T cur = vget<VT, T>(w, e);
-                            if (fix) cur = (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok);
-                            vset<VT, T>(w, e, update(cur, c, e, j));
-                        }
-                        row_st(reinterpret_cast<gptr<VT>>(Wi + j0), w);
-                    }
-                }
+                    if (all || c < nch)
+                        wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + (c < nch ? c : 0) * tpr * VE + tc * VE));
             }
         }
-        if (kEarlyRows<NT> && xg + B * rg < nrows) load_group(xg + B * rg);
+    };
+    auto sweep_unit = [&](int i0, int nr, const T *sq, const int *srl) {
+#pragma unroll
+        for (int g = 0; g < B; ++g) {
+            const int x = rsub + g * rg;
+            if (x >= nr) continue;
+            const int rn = srl[x];
+            if (i0 + x == rp || rn < 0) continue;   // pivot row: written at step k+1
+            sweep_row(g, i0 + x, sq[x], rn);
+        }
+    };
+
+    if constexpr (!CNT) {   // own rows only
+        if (kEarlyRows<NT> && !early) load_rows(r0, min(U, nsr), s_rls, false);
+        for (int xg = 0; xg < nsr; xg += U) {
+            sweep_unit(r0 + xg, min(U, nsr - xg), s_qs + xg, s_rls + xg);
+            if (kEarlyRows<NT> && xg + U < nsr)
+                load_rows(r0 + xg + U, min(U, nsr - xg - U), s_rls + xg + U, false);
+        }
+    } else {
+    // The units in sweep order: the workgroup's own (positions 0 .. nstat-1,
+    // multipliers already in LDS, no barrier), then units from the counter.
+    // A counted unit's multipliers and indices pass through LDS together
+    // with the id of the unit after it (the multiplier a_ik is overwritten
+    // during the sweep by whichever thread holds that column, so it is read
+    // before the barrier that precedes the sweep).  Thread 0 reads the
+    // counter one unit before the id is published; the first read happens
+    // during the second-to-last own unit, so the reads of different
+    // workgroups are spread over the step and their latency is hidden.
+    const gptr<int32_t> tick = &hdr->ticket[k & 1];
+    int tk = 0;
+    auto take = [&]() { tk = __hip_atomic_fetch_add(tick, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    T qv = (T)0;
+    int rov = 0;
+    // the next unit's multiplier and old logical row index for thread t,
+    // requested ahead of this unit's stores (nobody else writes its rows, and
+    // the publishing barrier then does not wait for the stores)
+    auto load_meta = [&](int uu) {
+        const int i0 = uu * U + min(t, U - 1);
+        const int i = (uu < nunits && i0 < n) ? i0 : rp;
+        qv = W[(int64_t)i * ldw + cp];
+        rov = rl_old[i];
+    };
+    auto publish = [&](int pr, int uu) {
+        const int i = uu * U + t;
+        if (t < U && i < n) row_meta(i, qv, rov, s_qd[pr], s_rld[pr], t);
+        if (t == 0) {
+            const int u2 = dyn0 + tk;
+            s_nx[pr] = u2;
+            if (u2 < nunits) take();
+        }
+    };
+    const int tj = max(nstat - 2, 0);   // position during which the first counter read happens
+    int u = nstat > 0 ? s0 : nunits, d1 = nunits, par = 1;
+    const T *sq = s_qs;
+    const int *srl = s_rls;
+    for (int j = 0; u < nunits; ++j) {
+        const bool next_counted = j + 1 >= nstat;
+        int un = next_counted ? (j + 1 == nstat ? d1 : s_nx[par]) : s0 + j + 1;
+        if (dyn) {
+            if (t == 0 && j == tj) take();
+            if (next_counted && !(nstat == 1 && j == 0)) load_meta(un);
+        }
+        const int nr = min(U, n - u * U);
+        if (kEarlyRows<NT> && !early) load_rows(u * U, nr, srl, false);   // det_only: after its barrier
+        sweep_unit(u * U, nr, sq, srl);
+        if (dyn && j == tj) {   // publish the first counted unit's id
+            if (t == 0) s_first = dyn0 + tk;
+            __syncthreads();
+            d1 = s_first;
+            if (t == 0 && d1 < nunits) take();
+            if (nstat == 1) { un = d1; load_meta(un); }
+        }
+        if (un >= nunits) break;
+        if (early) load_rows(un * U, min(U, n - un * U), s_rls, true);
+        if (!next_counted) {
+            sq = s_qs + (j + 1) * U;
+            srl = s_rls + (j + 1) * U;
+        } else {
+            par ^= 1;
+            publish(par, un);
+            __syncthreads();
+            sq = s_qd[par];
+            srl = s_rld[par];
+        }
+        u = un;
+    }
     }
     if (k + 1 < n) {
         const int any_nf = __syncthreads_or(nf ? 1 : 0);
@@ -581,7 +688,7 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int NT, bool NTL, bool FULL>
+template <typename T, int NT, bool NTL, bool FULL, bool CNT>
 static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDesc &single,
                             const int *grid_per_step,
                             int grid_init, int grid_finish, int max_n, int gather_grid,
@@ -595,7 +702,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         if (e != hipSuccess) return e;
     }
     for (int k = 0; k < max_n; ++k) {
-        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
+        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL, CNT>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
                            dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only,
                            run_flag);
         e = hipGetLastError();
@@ -615,29 +722,36 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
     return e;
 }
 
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, const BigDesc *descs,
-                      const int2 *bmap,
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted,
+                      const BigDesc *descs, const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
                       void *const *events, const int32_t *run_flag, hipStream_t s) {
+    // the counter is compiled in for full chunks below 1024 threads only
+    if (counted && !(full && nt < 1024)) return hipErrorInvalidValue;
 #define GJ_BIG_ARGS descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n, gather_grid, \
                     zero_tol, eps_default, det_only, events, run_flag, s
-#define GJ_BIG_CASE(TT, NTV)                                                               \
-    return nt_loads ? (full ? run_big_t<TT, NTV, true, true>(GJ_BIG_ARGS)                  \
-                            : run_big_t<TT, NTV, true, false>(GJ_BIG_ARGS))                \
-                    : (full ? run_big_t<TT, NTV, false, true>(GJ_BIG_ARGS)                 \
-                            : run_big_t<TT, NTV, false, false>(GJ_BIG_ARGS))
+#define GJ_BIG_CASE(TT, NTV)                                                                      \
+    if constexpr (NTV < 1024) {                                                                   \
+        if (counted)                                                                              \
+            return nt_loads ? run_big_t<TT, NTV, true, true, true>(GJ_BIG_ARGS)                   \
+                            : run_big_t<TT, NTV, false, true, true>(GJ_BIG_ARGS);                 \
+    }                                                                                             \
+    return nt_loads ? (full ? run_big_t<TT, NTV, true, true, false>(GJ_BIG_ARGS)                  \
+                            : run_big_t<TT, NTV, true, false, false>(GJ_BIG_ARGS))                \
+                    : (full ? run_big_t<TT, NTV, false, true, false>(GJ_BIG_ARGS)                 \
+                            : run_big_t<TT, NTV, false, false, false>(GJ_BIG_ARGS))
     if (fp32) {
         switch (nt) {
-            case 256: GJ_BIG_CASE(float, 256);
-            case 512: GJ_BIG_CASE(float, 512);
-            case 1024: GJ_BIG_CASE(float, 1024);
+            case 256: { GJ_BIG_CASE(float, 256); }
+            case 512: { GJ_BIG_CASE(float, 512); }
+            case 1024: { GJ_BIG_CASE(float, 1024); }
         }
     } else {
         switch (nt) {
-            case 256: GJ_BIG_CASE(double, 256);
-            case 512: GJ_BIG_CASE(double, 512);
-            case 1024: GJ_BIG_CASE(double, 1024);
+            case 256: { GJ_BIG_CASE(double, 256); }
+            case 512: { GJ_BIG_CASE(double, 512); }
+            case 1024: { GJ_BIG_CASE(double, 1024); }
         }
     }
 #undef GJ_BIG_CASE

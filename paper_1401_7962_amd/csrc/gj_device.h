@@ -264,6 +264,7 @@ struct BigHdr {
     int32_t status;       // 0 while running, else GJ_RES_* that stopped it
     int32_t rank;
     double tau;
+    int32_t ticket[2];    // work-unit counters of the step kernel, by step parity
 };
 
 // Global-address-space views of device pointers.  Pointers read from a
@@ -297,6 +298,7 @@ struct BigDesc {
     int64_t mstride;      // stride between the two parities of a map (= ldw)
     const int32_t *run;   // null, or a per-matrix flag: every kernel skips it when 0
     int32_t n, R, nblk, tpr;  // order, rows per workgroup, workgroups, threads per row
+    int32_t ustat;            // work units each workgroup of the step kernel takes statically
 };
 
 }  // namespace gj

@@ -27,7 +27,11 @@ hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks
                          double eps_default, int det_only, const int32_t *run_flag,
                          hipStream_t s);
 
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, const BigDesc *descs,
+// Streaming path: init, one step launch per k, finish, gather.  nt_loads:
+// nontemporal row loads; full: every matrix uses all register chunks;
+// counted: some descriptor leaves work units to the per-step counter
+// (needs full and nt < 1024).
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, const BigDesc *descs,
                       const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init,
                       int grid_finish, int max_n, int gather_grid, double zero_tol,

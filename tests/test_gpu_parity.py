@@ -104,6 +104,32 @@ def test_streaming_variants(gj, n, nt, rows, monkeypatch):
     _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n} nt={nt} rows={rows}")
 
 
+@pytest.mark.parametrize("n,rows,stat", [(250, 64, 1), (500, 64, 2), (1000, 32, 1), (1000, 32, 2),
+                                           (2000, 16, 3), (1000, 32, 100), (777, 16, 2)])
+def test_streaming_work_units(gj, n, rows, stat, monkeypatch):
+    """Work units of the step kernel taken by index and from the per-step
+    counter: one, two or three units per workgroup by index and the rest from
+    the counter (with one, the first counter read happens during the only own
+    unit; 250 and 500 end in a partial unit), every unit by index (100 is
+    clamped to the workgroup's share), and a size whose threads do not use all
+    their register chunks (no counter: every unit by index).  The inverse and
+    the determinant-only sweep (which skips the rows already eliminated) must
+    match the oracle bit for bit."""
+    import torch
+    monkeypatch.setenv("GJ_BIG_STATIC", str(stat))
+    if rows:
+        monkeypatch.setenv("GJ_BIG_ROWS", str(rows))
+    A = inputs.rng_for(0, 3200 + n).standard_normal((n, n))
+    want = oracle.gj_invert_f64(A)
+    _assert_same(A, _run_invert(gj, A), want, f"n={n} rows={rows} static={stat}")
+    ipiv, jpiv, res = gj.gj_det(_dev(A))
+    torch.cuda.synchronize()
+    r = gj.results_to_dicts(res)[0]
+    assert np.array_equal(ipiv.cpu().numpy(), want[1]) and np.array_equal(jpiv.cpu().numpy(), want[2])
+    assert r["det_mant"] == want[3]["det_mant"] and r["det_exp"] == want[3]["det_exp"]
+    assert r["det_sign"] == want[3]["det_sign"]
+
+
 @pytest.mark.parametrize("n", [4, 16, 64, 128, 256, 512])
 def test_hadamard_ties(gj, n):
     """Every candidate ties at every step: the tie-break on the swapped

@@ -76,6 +76,23 @@ def test_refined_inverse(gj, n, cond):
         assert abs(r["logabsdet"] - cf) <= 1e-9 * abs(cf)
 
 
+@pytest.mark.parametrize("stat", [1, 3])
+def test_refined_counted_units(gj, stat, monkeypatch):
+    """FP32 elimination with work units from the step kernel's counter (all
+    register chunks in use at n = 1000): the pivot sequence must be the FP32
+    oracle's, and the refined inverse as accurate as with the default split."""
+    monkeypatch.setenv("GJ_BIG_STATIC", str(stat))
+    monkeypatch.setenv("GJ_BIG_ROWS", "32")
+    n = 1000
+    A = inputs.conditioned(n, 1e4, inputs.rng_for(0, 6050 + stat))
+    X, ipiv, jpiv, r = _refined(gj, A)
+    assert r["code"] == 0, r
+    _, i32, j32, _ = oracle.gj_invert_f32(A.astype(np.float32))
+    assert np.array_equal(ipiv, i32) and np.array_equal(jpiv, j32)
+    Xo, _, _, _ = oracle.gj_invert_f64(A)
+    assert _rel(X, Xo) <= 1e-12
+
+
 @pytest.mark.parametrize("n", [64, 300])
 def test_refined_det_only(gj, n):
     A = inputs.conditioned(n, 1e3, inputs.rng_for(0, 6100 + n))
