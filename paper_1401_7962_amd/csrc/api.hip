@@ -166,12 +166,15 @@ BigShape big_shape(int n, bool fp32, int nt) {
     return s;
 }
 
-// Nontemporal row loads once the array swept per step outgrows the 256 MB
-// Infinity Cache (measured on MI355X: 8192^2 FP64 about 8% faster, 4096^2
-// FP64 about 9% slower with them).  GJ_BIG_NT=0/1 overrides.
+// Nontemporal row loads and stores once the array swept per step clearly
+// outgrows the 256 MB Infinity Cache.  Measured on MI355X (FP64, ms per
+// inversion, cached / nontemporal): 6144^2 = 288 MiB 758 / 841, 6656^2 =
+// 338 MiB 1077 / 1050, 7168^2 1219 / 1180, 8192^2 1661 / 1540.  Arrays the
+// cache holds lose with them (8192^2 FP32, 256 MiB: 13%; 4096^2 FP64: 9% with
+// the loads alone, 6% with the stores alone).  GJ_BIG_NT=0/1 overrides.
 bool big_nt_loads(size_t swept_bytes) {
     const int e = env_int("GJ_BIG_NT", -1);
-    return e >= 0 ? e != 0 : swept_bytes > ((size_t)256 << 20);
+    return e >= 0 ? e != 0 : swept_bytes > ((size_t)320 << 20);
 }
 size_t big_swept_bytes(const BigShape &s, bool fp32) {
     return (size_t)s.n * (size_t)s.ldw * (fp32 ? 4 : 8);

@@ -40,8 +40,10 @@ template <> struct VecOf<double> { static constexpr int V = 2; using type = doub
 template <> struct VecOf<float> { static constexpr int V = 4; using type = float4; using itype = int4; };
 
 // Row traffic of the working array (one 16-byte vector per access).  With
-// NTL the loads are nontemporal: once the swept array is larger than the
-// Infinity Cache nothing read in a step is read again before it is evicted.
+// NTL the loads and stores are nontemporal: once the swept array is larger
+// than the Infinity Cache nothing read or written in a step is used again
+// before it is evicted (with the stores too, 8192^2 FP64 steps run 9% faster;
+// a cache-resident array runs 2-6% slower with them).
 template <typename VT> struct NVec;
 template <> struct NVec<double2> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct NVec<float4> { typedef float type __attribute__((ext_vector_type(4))); };
@@ -56,7 +58,16 @@ template <bool NTL, typename VT> __device__ __forceinline__ VT row_ld(gptr<const
         return *p;
     }
 }
-template <typename VT> __device__ __forceinline__ void row_st(gptr<VT> p, const VT &v) { *p = v; }
+template <bool NTL, typename VT> __device__ __forceinline__ void row_st(gptr<VT> p, const VT &v) {
+    if constexpr (NTL) {
+        using NV = typename NVec<VT>::type;
+        NV nv;
+        __builtin_memcpy(&nv, &v, sizeof(NV));
+        __builtin_nontemporal_store(nv, reinterpret_cast<gptr<NV>>(p));
+    } else {
+        *p = v;
+    }
+}
 
 template <typename VT, typename T>
 __device__ inline T vget(const VT &x, int e) { return reinterpret_cast<const T *>(&x)[e]; }
@@ -462,7 +473,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                                     update(vget<VT, T>(wb[g][c], e), c, e, c * tpr * VE + tc * VE + e));
 #pragma unroll
             for (int c = 0; c < kNch; ++c)
-                if (FULL || c < nch) row_st(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
+                if (FULL || c < nch) row_st<NTL>(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
         } else {
 #pragma unroll
             for (int c = 0; c < kNch; ++c) {
@@ -476,7 +487,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                         if (fix) cur = (j == cpp) ? yp : div_pivot(cur, pp, yp, pp_ok);
                         vset<VT, T>(w, e, update(cur, c, e, j));
                     }
-                    row_st(reinterpret_cast<gptr<VT>>(Wi + j0), w);
+                    row_st<NTL>(reinterpret_cast<gptr<VT>>(Wi + j0), w);
                 }
             }
         }
