@@ -460,8 +460,9 @@ static hipError_t launch_cls(const MatDesc *mats, const OnchipTask *tasks, int n
                              const int32_t *run_flag, hipStream_t s) {
     if (mats) {
         int dev = 0, cus = 256, per = 1;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gj_onchip_kernel<T, KIND, E>, 256, 0) != hipSuccess) per = 1;
         const int force = env_int("GJ_ONCHIP_PER_CU", 0);   // experiments only
         if (force > 0) per = force;
