@@ -18,6 +18,8 @@ that are plain definitions written out in NumPy / Python:
 * ``residual`` -- ||A X - I||_F / (||A||_F ||X||_F);
 * ``cofactor_det`` -- exact rational Laplace expansion (n <= 7), the
   brute-force determinant pin;
+* ``gj_solve_f64`` -- the augmented elimination with a general right-hand
+  side B in place of I (eq. 2), giving A^-1 B;
 * ``perms_from_pivots`` -- original-index permutations from ipiv / jpiv.
 """
 from __future__ import annotations
@@ -85,6 +87,10 @@ def _load():
             fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P, P, P,
                            ctypes.POINTER(OraResult), ctypes.c_int, P]
             fn.restype = ctypes.c_int
+        lib.ora_gj_solve_f64.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int64, P,
+                                         ctypes.c_int64, ctypes.c_double, P, ctypes.c_int64,
+                                         P, P, ctypes.POINTER(OraResult)]
+        lib.ora_gj_solve_f64.restype = ctypes.c_int
         lib.ora_lu_static_det_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P,
                                               ctypes.POINTER(OraResult)]
         lib.ora_lu_static_det_f64.restype = ctypes.c_int
@@ -130,6 +136,26 @@ def gj_invert_f80(A, zero_tol: float = -1.0):
 def gj_augmented_f64(A, zero_tol: float = -1.0):
     """Literal eqs. 1-2, 14-15 on separate A and D arrays."""
     return _run("ora_gj_augmented_f64", A, zero_tol, np.float64, np.float64)
+
+
+def gj_solve_f64(A, B, zero_tol: float = -1.0):
+    """X = A^-1 B by the augmented elimination with D^0 = B (eqs. 1-2, 14-15;
+    column swaps undone as row swaps of D).  B is n x m.  Returns
+    (X, ipiv, jpiv, result dict); X is all NaN when the run stops early."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    if A.ndim != 2 or A.shape[0] != A.shape[1] or B.ndim != 2 or B.shape[0] != A.shape[0]:
+        raise ValueError("A must be n x n and B n x m")
+    n, m = A.shape[0], B.shape[1]
+    X = np.empty((n, m), dtype=np.float64)
+    ipiv = np.full(n, -1, dtype=np.int32)
+    jpiv = np.full(n, -1, dtype=np.int32)
+    res = OraResult()
+    code = _load().ora_gj_solve_f64(n, m, _ptr(A), n, _ptr(B), m, float(zero_tol), _ptr(X), m,
+                                    _ptr(ipiv), _ptr(jpiv), ctypes.byref(res))
+    if code < 0:
+        raise MemoryError("oracle solve: allocation failed")
+    return X, ipiv, jpiv, res.as_dict()
 
 
 def gj_first_steps(A, steps: int, zero_tol: float = -1.0, fp32: bool = False):

@@ -250,28 +250,31 @@ int ora_gj_invert_f80(int n, const double *A, int64_t lda, double zero_tol, doub
 }
 
 /*
- * Literal augmented form of eqs. 1-2 and 14-15: A and D held in separate
- * arrays.  Row swaps act on both halves (a left multiplication), column swaps
- * on A only.  At the end D = Q^-1 A^-1 where Q is the product of the column
- * swaps, so A^-1 = Q D: the column swaps come back as row swaps of D, in
- * reverse order.  Used to check the in-place form against the equations as
- * printed.
+ * Literal augmented form of eqs. 1-2 and 14-15 with a general right-hand
+ * side: A (n x n) and D (n x m) held in separate arrays, D^0 = B (eq. 2 has
+ * D^0 = I; any B gives D^n = Q^-1 A^-1 B instead, since every row operation
+ * of the elimination is applied to D as printed).  Row swaps act on both
+ * halves (a left multiplication), column swaps on A only.  At the end
+ * D = Q^-1 A^-1 B where Q is the product of the column swaps, so
+ * A^-1 B = Q D: the column swaps come back as row swaps of D, in reverse
+ * order.  X (n x m, ld ldx) receives A^-1 B, all NaN when the run stops.
  */
-int ora_gj_augmented_f64(int n, const double *A, int64_t lda, double zero_tol, double *X,
-                         int32_t *ipiv, int32_t *jpiv, ora_result *res)
+int ora_gj_solve_f64(int n, int m, const double *A, int64_t lda, const double *B, int64_t ldb,
+                     double zero_tol, double *X, int64_t ldx, int32_t *ipiv, int32_t *jpiv,
+                     ora_result *res)
 {
     double *a = (double *)malloc(sizeof(double) * (size_t)n * n);
-    double *d = X;
-    if (!a) return -1;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            a[(int64_t)i * n + j] = A[(int64_t)i * lda + j];        /* eq. 1 */
-            d[(int64_t)i * n + j] = (i == j) ? 1.0 : 0.0;          /* eq. 2 */
-        }
+    double *d = (double *)malloc(sizeof(double) * (size_t)n * m);
+    if (!a || !d) { free(a); free(d); return -1; }
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) a[(int64_t)i * n + j] = A[(int64_t)i * lda + j];   /* eq. 1 */
+        for (int j = 0; j < m; ++j) d[(int64_t)i * m + j] = B[(int64_t)i * ldb + j];   /* eq. 2, D^0 = B */
+    }
     double tau = zero_tol;
     int sign = 1;
     double m_acc = 1.0;
     int64_t e_acc = 0;
+    int code = ORA_OK;
     res->refine_iters = 0;
     res->resid = NAN;
     for (int k = 0; k < n; ++k) {
@@ -283,19 +286,9 @@ int ora_gj_augmented_f64(int n, const double *A, int64_t lda, double zero_tol, d
                 if (!isfinite(v)) nonfinite = 1;
                 if (v > best) { best = v; r = i; c = j; }
             }
-        if (nonfinite) {
-            ora_fill_failure(res, ORA_NONFINITE, k, n, ipiv, jpiv);
-            for (int64_t t = 0; t < (int64_t)n * n; ++t) d[t] = NAN;
-            free(a);
-            return ORA_NONFINITE;
-        }
+        if (nonfinite) { ora_fill_failure(res, ORA_NONFINITE, k, n, ipiv, jpiv); code = ORA_NONFINITE; break; }
         if (k == 0 && zero_tol < 0) tau = (double)n * 0x1p-52 * best;
-        if (best == 0.0 || best < tau) {
-            ora_fill_failure(res, ORA_SINGULAR, k, n, ipiv, jpiv);
-            for (int64_t t = 0; t < (int64_t)n * n; ++t) d[t] = NAN;
-            free(a);
-            return ORA_SINGULAR;
-        }
+        if (best == 0.0 || best < tau) { ora_fill_failure(res, ORA_SINGULAR, k, n, ipiv, jpiv); code = ORA_SINGULAR; break; }
         ipiv[k] = r;
         jpiv[k] = c;
         if (r != k) {
@@ -303,9 +296,11 @@ int ora_gj_augmented_f64(int n, const double *A, int64_t lda, double zero_tol, d
                 double t = a[(int64_t)k * n + j];
                 a[(int64_t)k * n + j] = a[(int64_t)r * n + j];
                 a[(int64_t)r * n + j] = t;
-                t = d[(int64_t)k * n + j];
-                d[(int64_t)k * n + j] = d[(int64_t)r * n + j];
-                d[(int64_t)r * n + j] = t;
+            }
+            for (int j = 0; j < m; ++j) {
+                double t = d[(int64_t)k * m + j];
+                d[(int64_t)k * m + j] = d[(int64_t)r * m + j];
+                d[(int64_t)r * m + j] = t;
             }
             sign = -sign;
         }
@@ -326,37 +321,53 @@ int ora_gj_augmented_f64(int n, const double *A, int64_t lda, double zero_tol, d
             m_acc = frexp(m_acc, &e2);
             e_acc += e2;
         }
-        for (int j = 0; j < n; ++j) {                       /* eq. 14 */
-            a[(int64_t)k * n + j] = a[(int64_t)k * n + j] / p;
-            d[(int64_t)k * n + j] = d[(int64_t)k * n + j] / p;
-        }
-        for (int i = 0; i < n; ++i) {                       /* eq. 15 */
+        for (int j = 0; j < n; ++j) a[(int64_t)k * n + j] = a[(int64_t)k * n + j] / p;   /* eq. 14 */
+        for (int j = 0; j < m; ++j) d[(int64_t)k * m + j] = d[(int64_t)k * m + j] / p;
+        for (int i = 0; i < n; ++i) {                                                   /* eq. 15 */
             if (i == k) continue;
             double q = a[(int64_t)i * n + k];
-            for (int j = 0; j < n; ++j) {
+            for (int j = 0; j < n; ++j)
                 a[(int64_t)i * n + j] = fma(-q, a[(int64_t)k * n + j], a[(int64_t)i * n + j]);
-                d[(int64_t)i * n + j] = fma(-q, d[(int64_t)k * n + j], d[(int64_t)i * n + j]);
-            }
+            for (int j = 0; j < m; ++j)
+                d[(int64_t)i * m + j] = fma(-q, d[(int64_t)k * m + j], d[(int64_t)i * m + j]);
         }
     }
-    for (int k = n - 1; k >= 0; --k) {                      /* A^-1 = Q D */
-        int c = jpiv[k];
-        if (c != k)
-            for (int j = 0; j < n; ++j) {
-                double t = d[(int64_t)k * n + j];
-                d[(int64_t)k * n + j] = d[(int64_t)c * n + j];
-                d[(int64_t)c * n + j] = t;
-            }
+    if (code == ORA_OK) {
+        for (int k = n - 1; k >= 0; --k) {                                              /* A^-1 B = Q D */
+            int c = jpiv[k];
+            if (c != k)
+                for (int j = 0; j < m; ++j) {
+                    double t = d[(int64_t)k * m + j];
+                    d[(int64_t)k * m + j] = d[(int64_t)c * m + j];
+                    d[(int64_t)c * m + j] = t;
+                }
+        }
+        res->code = ORA_OK;
+        res->rank = n;
+        res->det_sign = (m_acc < 0) ? -sign : sign;
+        res->det_mant = fabs(m_acc);
+        res->det_exp = e_acc;
+        res->det = ora_ldexp64((double)sign * m_acc, e_acc);
+        res->logabsdet = log(res->det_mant) + (double)e_acc * 0.69314718055994530942;
     }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < m; ++j)
+            X[(int64_t)i * ldx + j] = (code == ORA_OK) ? d[(int64_t)i * m + j] : NAN;
     free(a);
-    res->code = ORA_OK;
-    res->rank = n;
-    res->det_sign = (m_acc < 0) ? -sign : sign;
-    res->det_mant = fabs(m_acc);
-    res->det_exp = e_acc;
-    res->det = ora_ldexp64((double)sign * m_acc, e_acc);
-    res->logabsdet = log(res->det_mant) + (double)e_acc * 0.69314718055994530942;
-    return ORA_OK;
+    free(d);
+    return code;
+}
+
+/* The augmented form with D^0 = I (eq. 2 as printed): X receives A^-1. */
+int ora_gj_augmented_f64(int n, const double *A, int64_t lda, double zero_tol, double *X,
+                         int32_t *ipiv, int32_t *jpiv, ora_result *res)
+{
+    double *eye = (double *)calloc((size_t)n * n, sizeof(double));
+    if (!eye) return -1;
+    for (int i = 0; i < n; ++i) eye[(int64_t)i * n + i] = 1.0;
+    int code = ora_gj_solve_f64(n, n, A, lda, eye, n, zero_tol, X, n, ipiv, jpiv, res);
+    free(eye);
+    return code;
 }
 
 /*

@@ -116,3 +116,80 @@ def test_mutant_is_caught(tmp_path, name):
     fn = _build(tmp_path, name, old, new)
     failed = _pin_battery(fn)
     assert failed, f"mutant {name} passed every pin"
+
+
+# Planted mistakes in the right-hand-side half of the augmented elimination
+# (the solve); checked by a battery of the solve pins' kinds.
+SOLVE_MUTANTS = {
+    "rhs_not_divided": ("for (int j = 0; j < m; ++j) d[(int64_t)k * m + j] = d[(int64_t)k * m + j] / p;",
+                        "(void)0;"),
+    "rhs_not_row_swapped": ("                double t = d[(int64_t)k * m + j];\n                d[(int64_t)k * m + j] = d[(int64_t)r * m + j];",
+                            "                double t = d[(int64_t)k * m + j];\n                d[(int64_t)k * m + j] = d[(int64_t)k * m + j];"),
+    "no_final_row_permutation": ("for (int k = n - 1; k >= 0; --k) {                                              /* A^-1 B = Q D */",
+                                 "for (int k = n - 1; k >= 0 && 0; --k) {"),
+    "rhs_update_sign": ("d[(int64_t)i * m + j] = fma(-q, d[(int64_t)k * m + j], d[(int64_t)i * m + j]);",
+                        "d[(int64_t)i * m + j] = fma(q, d[(int64_t)k * m + j], d[(int64_t)i * m + j]);"),
+}
+
+
+def _build_solve(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert old in src, f"mutation anchor for {name} not found"
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(src.replace(old, new))
+    subprocess.run(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-o", str(so), str(c), "-lm"], check=True)
+    fn = ctypes.CDLL(str(so)).ora_gj_solve_f64
+    P = ctypes.c_void_p
+    fn.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int64, P, ctypes.c_int64,
+                   ctypes.c_double, P, ctypes.c_int64, P, P, ctypes.POINTER(oracle.OraResult)]
+    return fn
+
+
+def _solve(fn, A, B):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    n, m = A.shape[0], B.shape[1]
+    X = np.empty((n, m))
+    ipiv = np.full(n, -1, np.int32)
+    jpiv = np.full(n, -1, np.int32)
+    res = oracle.OraResult()
+    P = ctypes.c_void_p
+    fn(n, m, A.ctypes.data_as(P), n, B.ctypes.data_as(P), m, -1.0, X.ctypes.data_as(P), m,
+       ipiv.ctypes.data_as(P), jpiv.ctypes.data_as(P), ctypes.byref(res))
+    return X, res.as_dict()
+
+
+def _solve_battery(fn):
+    failed = []
+    with np.errstate(all="ignore"):
+        rng = inputs.rng_for(0, 711)
+        B = rng.integers(-50, 50, size=(4, 3)).astype(np.float64)
+        Pm = np.zeros((4, 4))
+        Pm[np.arange(4), [2, 0, 3, 1]] = 1
+        X, res = _solve(fn, Pm, B)
+        if not np.array_equal(X, Pm.T @ B):
+            failed.append("permutation")
+        D = np.diag([2.0, -0.25, 8.0, 0.5])
+        X, res = _solve(fn, D, B)
+        if not np.array_equal(X, B / np.diag(D)[:, None]):
+            failed.append("diagonal")
+        A = rng.standard_normal((12, 12))
+        Bn = rng.standard_normal((12, 3))
+        X, res = _solve(fn, A, Bn)
+        if not (res["code"] == 0 and np.abs(A @ X - Bn).max() <= 1e-12 * np.abs(Bn).max() * np.linalg.cond(A)):
+            failed.append("residual")
+    return failed
+
+
+def test_unmutated_solve_passes_battery(tmp_path):
+    fn = _build_solve(tmp_path, "solve_identity", "#include <math.h>", "#include <math.h>")
+    assert _solve_battery(fn) == []
+
+
+@pytest.mark.parametrize("name", sorted(SOLVE_MUTANTS))
+def test_solve_mutant_is_caught(tmp_path, name):
+    old, new = SOLVE_MUTANTS[name]
+    fn = _build_solve(tmp_path, name, old, new)
+    assert _solve_battery(fn), f"mutant {name} passed every pin"

@@ -196,6 +196,91 @@ def test_augmented_form_is_bitwise_equal():
         assert res["det_mant"] == res2["det_mant"] and res["det_exp"] == res2["det_exp"]
 
 
+def _exact_solve(A, B):
+    """A^-1 B in rationals: Gauss-Jordan with exact arithmetic (textbook; any
+    nonzero pivot will do when nothing is rounded)."""
+    n, m = len(A), len(B[0])
+    M = [[Fraction(x) for x in list(A[i]) + list(B[i])] for i in range(n)]
+    for k in range(n):
+        r = next(i for i in range(k, n) if M[i][k] != 0)
+        M[k], M[r] = M[r], M[k]
+        p = M[k][k]
+        M[k] = [x / p for x in M[k]]
+        for i in range(n):
+            if i != k and M[i][k] != 0:
+                q = M[i][k]
+                M[i] = [a - q * b for a, b in zip(M[i], M[k])]
+    return [[M[i][n + j] for j in range(m)] for i in range(n)]
+
+
+def test_solve_with_identity_is_the_inverse():
+    """D^0 = B in eq. 2: with B = I the augmented elimination is the inversion,
+    bit for bit, including ties (Hadamard), a permutation and singular input."""
+    rng = inputs.rng_for(0, 710)
+    mats = [rng.standard_normal((n, n)) for n in (1, 2, 5, 17, 40)]
+    mats += [inputs.sylvester_hadamard(8), inputs.pascal(3), np.zeros((3, 3)),
+             np.ones((4, 4))]
+    for A in mats:
+        n = A.shape[0]
+        X, ipiv, jpiv, res = oracle.gj_invert_f64(A)
+        Xs, ips, jps, rs = oracle.gj_solve_f64(A, np.eye(n))
+        assert np.array_equal(ipiv, ips) and np.array_equal(jpiv, jps)
+        assert res["code"] == rs["code"] and res["rank"] == rs["rank"]
+        if res["code"] == 0:
+            assert X.tobytes() == Xs.tobytes()
+            assert res["det_mant"] == rs["det_mant"] and res["det_exp"] == rs["det_exp"]
+            assert res["det_sign"] == rs["det_sign"]
+        else:
+            assert np.isnan(Xs).all()
+
+
+def test_solve_exact_cases():
+    """Inputs where every operation is exact: a permutation matrix (X = P^T B,
+    with column swaps undone as row swaps) and a power-of-two diagonal."""
+    rng = inputs.rng_for(0, 711)
+    B = rng.integers(-50, 50, size=(4, 3)).astype(np.float64)
+    s = [2, 0, 3, 1]
+    Pm = np.zeros((4, 4))
+    Pm[np.arange(4), s] = 1
+    X, ipiv, jpiv, res = oracle.gj_solve_f64(Pm, B)
+    assert res["code"] == 0 and res["det"] == -1
+    assert np.array_equal(X, Pm.T @ B)
+    D = np.diag([2.0, -0.25, 8.0, 0.5])
+    X, _, _, res = oracle.gj_solve_f64(D, B)
+    assert np.array_equal(X, B / np.diag(D)[:, None])
+    assert res["det"] == -2.0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_solve_against_exact_rationals(seed):
+    """Small integer systems solved exactly in rationals; the FP64 result must
+    be within the normwise bound c * n * u * cond(A) of the exact one."""
+    rng = inputs.rng_for(0, 720 + seed)
+    n, m = int(rng.integers(2, 7)), int(rng.integers(1, 4))
+    A = rng.integers(-9, 10, size=(n, n)).astype(np.float64)
+    while abs(np.linalg.det(A)) < 0.5:
+        A = rng.integers(-9, 10, size=(n, n)).astype(np.float64)
+    B = rng.integers(-9, 10, size=(n, m)).astype(np.float64)
+    Xe = np.array([[float(x) for x in row] for row in _exact_solve(A.tolist(), B.tolist())])
+    X, _, _, res = oracle.gj_solve_f64(A, B)
+    assert res["code"] == 0
+    cond = np.linalg.cond(A)
+    err = np.abs(X - Xe).max() / np.abs(Xe).max()
+    assert err <= 8 * n * 2.0 ** -53 * cond, (err, cond)
+
+
+def test_solve_columns_are_independent():
+    """Each column of B is carried by the same row operations: solving for
+    [B1 B2] gives, bit for bit, the solutions for B1 and B2 separately."""
+    rng = inputs.rng_for(0, 730)
+    A = rng.standard_normal((30, 30))
+    B = rng.standard_normal((30, 5))
+    X, *_ = oracle.gj_solve_f64(A, B)
+    X1, *_ = oracle.gj_solve_f64(A, B[:, :2])
+    X2, *_ = oracle.gj_solve_f64(A, B[:, 2:])
+    assert X.tobytes() == np.hstack([X1, X2]).tobytes()
+
+
 @pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
 def test_forward_error_against_long_double(cond):
     n = 48
