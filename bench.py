@@ -339,6 +339,44 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
     return out
 
 
+def bench_solve(n: int = 4096, m: int = 16, reps: int = 3):
+    """A X = B with m right-hand sides by the elimination of [A | B] (eq. 2
+    with D^0 = B), on the headline's 4096 input: time per solve, the step
+    kernel's rate over the n (n + m) array, and the normwise residual."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    A = torch.from_numpy(inputs.single_dominant(n)).to("cuda")
+    B = torch.from_numpy(inputs.rng_for(0, 4242).standard_normal((n, m))).to("cuda")
+    X = torch.empty((n, m), dtype=torch.float64, device="cuda")
+    ip = torch.empty(n, dtype=torch.int32, device="cuda")
+    jp = torch.empty_like(ip)
+    res = torch.empty(gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(gj.gj_workspace_size(gj.GJ_OP_SOLVE, n, [m]), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    gj.gj_solve(A, B, X, ip, jp, res, None, ws)
+    torch.cuda.synchronize()
+    e = _events(4 * reps, stream)
+    for k in range(reps):
+        o = gj.make_opts(step_events=(ctypes_ptr(e[4 * k + 1]), ctypes_ptr(e[4 * k + 2])))
+        e[4 * k].record()
+        gj.gj_solve(A, B, X, ip, jp, res, o, ws)
+        e[4 * k + 3].record()
+    torch.cuda.synchronize()
+    ms = min(e[4 * k].elapsed_time(e[4 * k + 3]) for k in range(reps))
+    steps_ms = min(e[4 * k + 1].elapsed_time(e[4 * k + 2]) for k in range(reps))
+    r = gj.results_to_dicts(res)[0]
+    resid = float(torch.linalg.norm(A @ X - B) / (torch.linalg.norm(A) * torch.linalg.norm(X)
+                                                  + torch.linalg.norm(B)))
+    per_launch_us = steps_ms * 1e3 / n
+    alg = 16.0 * n * (n + m)
+    gbs = alg / (per_launch_us * 1e-6) / 1e9
+    return {"n": n, "m": m, "ms": round(ms, 2), "solves_per_s": round(1e3 / ms, 3),
+            "code": r["code"], "resid": resid, "per_launch_us": round(per_launch_us, 2),
+            "alg_bytes_per_launch": int(alg), "achieved_gbs": round(gbs, 1),
+            "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def ctypes_ptr(event):
     """hipEvent_t handle of a torch.cuda.Event."""
     return event.cuda_event
@@ -369,7 +407,8 @@ def cpu_baseline(n: int = 4096, sample_steps: int = 256):
 LEGS = {"latency_small": lambda: bench_latency_small(),
         "batch_uneven_100k": lambda: bench_batch_uneven(),
         "conditioned_8192": lambda: bench_conditioned_8192(),
-        "batch_conditioned_20k": lambda: bench_batch_conditioned()}
+        "batch_conditioned_20k": lambda: bench_batch_conditioned(),
+        "solve_4096": lambda: bench_solve()}
 
 
 def main():
@@ -454,6 +493,9 @@ def main():
         torch.cuda.empty_cache()
         extras["batch_conditioned_20k"] = bench_batch_conditioned()
         print("bench: 20k refined batch done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["solve_4096"] = bench_solve()
+        print("bench: solve done", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["extras"] = extras
     if not args.no_cpu_baseline:

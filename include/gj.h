@@ -83,7 +83,7 @@ enum {
 };
 
 /* gj_workspace_size op codes */
-enum { GJ_OP_INVERT = 0, GJ_OP_DET = 1, GJ_OP_INVERT_BATCHED = 2 };
+enum { GJ_OP_INVERT = 0, GJ_OP_DET = 1, GJ_OP_INVERT_BATCHED = 2, GJ_OP_SOLVE = 3 };
 
 /* Per-matrix result, written to device memory by every entry point. */
 typedef struct gj_result {
@@ -163,10 +163,37 @@ gj_status gj_det(int32_t n, const double *A, int64_t lda, int32_t *ipiv, int32_t
                  void *stream);
 
 /*
+ * gj_solve -- X = A^-1 B for one n x n matrix and m right-hand sides.  Runs
+ * the elimination of gj_invert on the augmented array [A | B] (eq. 2 with
+ * D^0 = B in place of I; eqs. 14-15 update both parts; B's columns are never
+ * pivot candidates), so the pivot sequence and the determinant equal those
+ * of gj_invert bit for bit.  The column swaps of A come back as row swaps of
+ * the result (Obs. 3).
+ *   n          order, 1 <= n, and n + m <= 16384
+ *   m          number of right-hand sides, >= 1
+ *   A, lda     input matrix (FP64, row-major), read only
+ *   B, ldb     right-hand sides (n x m, FP64, row-major), read only
+ *   X, ldx     output (n x m, FP64); must overlap neither A, B nor ws; all NaN
+ *              when the matrix is singular or non-finite
+ *   ipiv, jpiv n int32 each: the pivot sequence (see Pivots above)
+ *   res        one gj_result (resid is NaN)
+ *   opts       NULL or options with precision GJ_PREC_FP64 and want_resid 0
+ *              (else GJ_E_UNSUPPORTED); zero_tol as for gj_invert
+ *   ws         workspace of gj_workspace_size(GJ_OP_SOLVE, n, &m, opts) bytes,
+ *              256-byte aligned
+ * Every order goes through the streaming kernels.
+ * Paper: eqs. 1-2 (with D^0 = B), 13-15, Obs. 2-3.
+ */
+gj_status gj_solve(int32_t n, int32_t m, const double *A, int64_t lda, const double *B,
+                   int64_t ldb, double *X, int64_t ldx, int32_t *ipiv, int32_t *jpiv,
+                   gj_result *res, const gj_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * gj_workspace_size -- bytes of workspace needed.
  *   op          GJ_OP_INVERT or GJ_OP_DET: n_or_batch = n, n_host unused;
  *               GJ_OP_INVERT_BATCHED: n_or_batch = batch, n_host = HOST array of
- *               orders.
+ *               orders;
+ *               GJ_OP_SOLVE: n_or_batch = n, n_host = HOST pointer to m (one int32).
  * Returns 0 for invalid arguments.
  */
 size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,

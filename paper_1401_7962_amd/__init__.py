@@ -21,7 +21,7 @@ GJ_OK, GJ_E_INVALID_ARG, GJ_E_WORKSPACE, GJ_E_HIP, GJ_E_UNSUPPORTED = 0, -1, -2,
 GJ_RES_OK, GJ_RES_SINGULAR, GJ_RES_NONFINITE, GJ_RES_REFINE_FALLBACK = 0, 1, 2, 3
 GJ_PREC_FP64, GJ_PREC_FP32_REFINED = 0, 1
 GJ_FLAG_REUSE_PLAN = 1
-GJ_OP_INVERT, GJ_OP_DET, GJ_OP_INVERT_BATCHED = 0, 1, 2
+GJ_OP_INVERT, GJ_OP_DET, GJ_OP_INVERT_BATCHED, GJ_OP_SOLVE = 0, 1, 2, 3
 
 
 class gj_result(ctypes.Structure):
@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
     lib.gj_invert_batched.restype = I32
     lib.gj_det.argtypes = [I32, P, I64, P, P, P, P, P, SZ, P]
     lib.gj_det.restype = I32
+    lib.gj_solve.argtypes = [I32, I32, P, I64, P, I64, P, I64, P, P, P, P, P, SZ, P]
+    lib.gj_solve.restype = I32
     lib.gj_workspace_size.argtypes = [I32, I32, P, P]
     lib.gj_workspace_size.restype = SZ
     lib.gj_status_string.argtypes = [I32]
@@ -88,7 +90,7 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-EXPORTS = ("gj_invert", "gj_invert_batched", "gj_det", "gj_workspace_size",
+EXPORTS = ("gj_invert", "gj_invert_batched", "gj_det", "gj_solve", "gj_workspace_size",
            "gj_status_string", "gj_onchip_max_n", "gj_dgemm")
 
 
@@ -203,6 +205,37 @@ def gj_dgemm(A, B, C=None, D=None, alpha=1.0, beta=0.0, gamma=0.0, stream=None):
                       _stream_ptr(stream))
     _check(st)
     return D
+
+
+def gj_solve(A, B, X=None, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = None, ws=None,
+             stream=None):
+    """X = A^-1 B for a square FP64 CUDA tensor A and an n x m FP64 CUDA
+    tensor B (both row-major).  Returns (X, ipiv, jpiv, res)."""
+    import torch
+    lib = load_library()
+    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.float64 or not A.is_cuda:
+        raise GJError("A must be a square float64 CUDA tensor")
+    if B.dim() != 2 or B.shape[0] != A.shape[0] or B.dtype != torch.float64 or not B.is_cuda:
+        raise GJError("B must be an n x m float64 CUDA tensor")
+    if A.stride(1) != 1 or B.stride(1) != 1:
+        raise GJError("A and B must be row-major (unit column stride)")
+    n, m = A.shape[0], B.shape[1]
+    dev = A.device
+    X = torch.empty((n, m), dtype=torch.float64, device=dev) if X is None else X
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev) if ipiv is None else ipiv
+    jpiv = torch.empty(n, dtype=torch.int32, device=dev) if jpiv is None else jpiv
+    res = _res_tensor(1, dev) if res is None else res
+    need = gj_workspace_size(GJ_OP_SOLVE, n, [m], opts)
+    if need == 0:
+        raise GJError("gj_solve: unsupported size or options")
+    if ws is None:
+        ws = _workspace(need, dev)
+    st = lib.gj_solve(n, m, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(X), X.stride(0),
+                      _ptr(ipiv), _ptr(jpiv), _ptr(res),
+                      ctypes.byref(opts) if opts is not None else None, _ptr(ws),
+                      ws.numel() * ws.element_size(), _stream_ptr(stream))
+    _check(st)
+    return X, ipiv, jpiv, res
 
 
 def gj_det(A, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = None, ws=None, stream=None):

@@ -108,7 +108,8 @@ const TuneEntry *tuned(bool fp32, int n) {
 
 // ------------------------------------------------------ streaming-path plan
 struct BigShape {
-    int n, nt, tpr, R, nblk;
+    int n, ncol, nt, tpr, R, nblk;   // ncol: columns of W in use (n, or rhs0 + m for a solve)
+    int rhs0;                        // column of W holding B's first column (n when not solving)
     int nunits, share;   // work units of a step; units per workgroup
     int ustat;           // units per workgroup taken by index (the rest by counter)
     int64_t ldw;
@@ -123,14 +124,17 @@ int big_threads(int n, bool fp32) {
     return 1024;
 }
 
-BigShape big_shape(int n, bool fp32, int nt) {
+BigShape big_shape(int n, bool fp32, int nt, int ncol = 0) {
     BigShape s;
     const int ve = fp32 ? 4 : 2;
+    if (ncol < n) ncol = n;
     s.n = n;
+    s.ncol = ncol;
+    s.rhs0 = n;
     s.nt = nt;
     // threads per row: just enough for 8 vector chunks per thread, so that
     // every thread's registers are used (a wavefront may span several rows)
-    int need = (n + 8 * ve - 1) / (8 * ve);
+    int need = (ncol + 8 * ve - 1) / (8 * ve);
     int tpr = 4;
     while (tpr < need) tpr <<= 1;
     if (tpr > nt) tpr = nt;
@@ -155,14 +159,14 @@ BigShape big_shape(int n, bool fp32, int nt) {
     // share left to the counter (GJ_BIG_STATIC overrides); the counter is
     // compiled only into the full-chunk kernels below 1024 threads
     const int per = tpr * (fp32 ? 4 : 2);
-    const bool cnt_ok = (n + per - 1) / per == 8 && nt < 1024;
+    const bool cnt_ok = (ncol + per - 1) / per == 8 && nt < 1024;
     int pct = env_int("GJ_BIG_COUNTED", -1);
     if (pct < 0 || pct > 90) pct = te ? te->counted : 0;
     int S = env_int("GJ_BIG_STATIC", 0);
     if (S <= 0) S = s.share - (s.share * pct + 50) / 100;
     s.ustat = cnt_ok ? std::max(1, std::min(S, s.share)) : s.share;
     const int64_t chunk = (int64_t)tpr * ve;
-    s.ldw = ((int64_t)n + chunk - 1) / chunk * chunk + env_int("GJ_BIG_PAD", 0) * ve;
+    s.ldw = ((int64_t)ncol + chunk - 1) / chunk * chunk + env_int("GJ_BIG_PAD", 0) * ve;
     return s;
 }
 
@@ -187,7 +191,7 @@ bool big_counted(const BigShape &s) {
 // then compiles without the per-chunk tests).
 bool big_full(const BigShape &s, bool fp32) {
     const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
-    return (s.n + per - 1) / per == 8;
+    return (s.ncol + per - 1) / per == 8;
 }
 
 // Byte layout of one matrix's streaming-path buffers, relative to `base`.
@@ -237,6 +241,8 @@ BigDesc make_desc(const BigShape &s, const BigBufs &b, char *ws, const double *A
     d.nblk = s.nblk;
     d.tpr = s.tpr;
     d.ustat = s.ustat;
+    d.ncol = s.ncol;
+    d.rhs0 = s.rhs0;
     return d;
 }
 
@@ -361,6 +367,48 @@ size_t single_ws(int n, const Opts &o, bool det_only) {
     return need;
 }
 
+// A X = B through the streaming elimination on [A | B] (every order; the
+// on-chip kernels hold no right-hand sides).  When A alone fills all 8
+// register chunks of its own row shape and B fits one more chunk, B becomes
+// that extra partial chunk and the inversion's row shape is kept (rhs);
+// otherwise [A | B] is shaped as one wider array, B right after A.
+BigShape big_shape_solve(int n, int m, bool &rhs) {
+    const int nt = big_threads(n, false);
+    BigShape s = big_shape(n, false, nt);
+    rhs = big_full(s, false) && nt < 1024 && m <= s.tpr * 2;
+    if (rhs) {
+        s.rhs0 = 8 * s.tpr * 2;
+        s.ncol = s.rhs0 + m;
+        s.ldw = s.rhs0 + (m + 15) / 16 * 16;   // rows stay 128-byte aligned
+        s.ustat = s.share;                     // the extra chunk is built without the counter
+        return s;
+    }
+    return big_shape(n, false, big_threads(n + m, false), n + m);
+}
+
+size_t solve_ws(int n, int m) {
+    bool rhs;
+    return big_bufs(big_shape_solve(n, m, rhs), false, 0).end;
+}
+
+gj_status run_solve(int n, int m, const double *A, int64_t lda, const double *B, int64_t ldb,
+                    double *X, int64_t ldx, int32_t *ipiv, int32_t *jpiv, gj_result *res,
+                    const Opts &o, void *ws, size_t ws_bytes, hipStream_t s) {
+    bool rhs;
+    BigShape sh = big_shape_solve(n, m, rhs);
+    BigBufs bb = big_bufs(sh, false, 0);
+    if (ws_bytes < bb.end) return GJ_E_WORKSPACE;
+    BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
+    d.B = B;
+    d.ldb = ldb;
+    hipError_t e = launch_big(false, sh.nt, big_nt_loads(big_swept_bytes(sh, false)),
+                              rhs || big_full(sh, false), !rhs && big_counted(sh), rhs, nullptr,
+                              nullptr, d, nullptr, sh.nblk, sh.nblk, n, sh.nblk, o.zero_tol,
+                              kEps64, 0, o.events, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e);
+    return GJ_OK;
+}
+
 gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx, int32_t *ipiv,
                      int32_t *jpiv, gj_result *res, const Opts &o, void *ws, size_t ws_bytes,
                      hipStream_t s, bool det_only) {
@@ -394,7 +442,7 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
     BigBufs bb = big_bufs(sh, fp32, 0);
     if (ws_bytes < bb.end) return GJ_E_WORKSPACE;
     BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
-    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32), big_counted(sh),
+    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32), big_counted(sh), false,
                               nullptr, nullptr,
                               d, nullptr, sh.nblk, sh.nblk, n,
                               det_only ? 0 : sh.nblk, o.zero_tol, eps_default, det_only ? 1 : 0,
@@ -485,7 +533,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, true, nt);
         BigBufs bb = big_bufs(sh, true, L.big32);
         d32 = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true), big_counted(sh),
+        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true), big_counted(sh), false,
                           nullptr, nullptr, d32,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, 0.0, 0.0, det_only ? 1 : 0, o.events, nullptr, s));
@@ -549,7 +597,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, false, nt);
         BigBufs bb = big_bufs(sh, false, L.over64);
         BigDesc d = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false), big_counted(sh),
+        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false), big_counted(sh), false,
                           nullptr, nullptr, d,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
@@ -1008,7 +1056,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)E.bmap.size();
-        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full, E.big_counted,
+        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full, E.big_counted, false,
                           reinterpret_cast<const BigDesc *>(w + E.off_descs),
                           reinterpret_cast<const int2 *>(w + E.off_bmap), BigDesc(),
                           E.grid_per_step.data(), nb, nb, E.big_max_n, nb, 0.0, 0.0, 0, o.events,
@@ -1035,7 +1083,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)P.fb_bmap.size();
-        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full, P.fb_counted,
+        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full, P.fb_counted, false,
                           reinterpret_cast<const BigDesc *>(w + P.off_fb_descs),
                           reinterpret_cast<const int2 *>(w + P.off_fb_bmap), BigDesc(),
                           P.fb_grid.data(), nb, nb, E.big_max_n, nb, o.zero_tol, kEps64, 0, nullptr,
@@ -1144,6 +1192,11 @@ size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
         if (n_or_batch < 1 || n_or_batch > kMaxN) return 0;
         return single_ws(n_or_batch, o, op == GJ_OP_DET);
     }
+    if (op == GJ_OP_SOLVE) {
+        if (n_or_batch < 1 || !n_host || n_host[0] < 1 || n_or_batch + n_host[0] > kMaxN) return 0;
+        if (o.precision != GJ_PREC_FP64 || o.want_resid) return 0;
+        return solve_ws(n_or_batch, n_host[0]);
+    }
     if (op == GJ_OP_INVERT_BATCHED) {
         if (n_or_batch < 1 || !n_host) return 0;
         if (o.precision == GJ_PREC_FP32_REFINED) {
@@ -1209,6 +1262,32 @@ gj_status gj_det(int32_t n, const double *A, int64_t lda, int32_t *ipiv, int32_t
         if (o.precision == GJ_PREC_FP32_REFINED)
             return run_refined_single(n, A, lda, nullptr, n, ipiv, jpiv, res, o, (char *)ws, s, true);
         return run_single(n, A, lda, nullptr, n, ipiv, jpiv, res, o, ws, ws_bytes, s, true);
+    } catch (...) {
+        return GJ_E_HIP;
+    }
+}
+
+gj_status gj_solve(int32_t n, int32_t m, const double *A, int64_t lda, const double *B,
+                   int64_t ldb, double *X, int64_t ldx, int32_t *ipiv, int32_t *jpiv,
+                   gj_result *res, const gj_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+    try {
+        Opts o;
+        if (!read_opts(opts, o)) return GJ_E_INVALID_ARG;
+        if (n < 1 || m < 1 || lda < n || ldb < m || ldx < m || !A || !B || !X || !ipiv || !jpiv ||
+            !res)
+            return GJ_E_INVALID_ARG;
+        if ((int64_t)n + m > kMaxN || o.precision != GJ_PREC_FP64 || o.want_resid)
+            return GJ_E_UNSUPPORTED;
+        const size_t abytes = ((size_t)(n - 1) * lda + n) * 8;
+        const size_t bbytes = ((size_t)(n - 1) * ldb + m) * 8, xbytes = ((size_t)(n - 1) * ldx + m) * 8;
+        if (overlaps(A, abytes, X, xbytes) || overlaps(B, bbytes, X, xbytes)) return GJ_E_INVALID_ARG;
+        if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
+        if (ws_bytes < solve_ws(n, m)) return GJ_E_WORKSPACE;
+        if (overlaps(ws, ws_bytes, X, xbytes) || overlaps(ws, ws_bytes, A, abytes) ||
+            overlaps(ws, ws_bytes, B, bbytes))
+            return GJ_E_INVALID_ARG;
+        return run_solve(n, m, A, lda, B, ldb, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes,
+                         (hipStream_t)stream);
     } catch (...) {
         return GJ_E_HIP;
     }
@@ -1296,7 +1375,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         }
         if (!P.big_members.empty()) {
             const int nb = (int)P.bmap.size();
-            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full, P.big_counted,
+            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full, P.big_counted, false,
                                       reinterpret_cast<const BigDesc *>(w + P.off_descs),
                                       reinterpret_cast<const int2 *>(w + P.off_bmap), BigDesc(),
                                       P.grid_per_step.data(), nb, nb, P.big_max_n, nb, o.zero_tol,

@@ -31,6 +31,13 @@
 //     needed.
 //   * The final depivoting (Obs. 3) is a gather:
 //       X(i, j) = W(rowphys[collog[i]], colphys[rowlog[j]]).
+//   * Solving A X = B runs the same elimination on [A | B] (eq. 2 with
+//     D^0 = B): the m columns of B follow A's columns in W (from column
+//     rhs0: n, or the end of A's last register chunk), get the same eq. 14-15
+//     updates and are never pivot candidates.  The column swaps of A come
+//     back as row swaps of the result: X(i, j) = W(rowphys[collog[i]], rhs0 + j).
+#include <type_traits>
+
 #include "gj_device.h"
 
 namespace gj {
@@ -197,6 +204,7 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
         if (tc == 0) d.rowlog[i] = i;
         for (int j = tc; j < d.ldw; j += tpr) {
             T x = (T)0;
+            if (j >= d.rhs0 && j < d.ncol) x = (T)d.B[(int64_t)i * d.ldb + (j - d.rhs0)];   // solve: D^0 = B
             if (j < n) {
                 x = (T)d.A[(int64_t)i * d.lda + j];
                 const double ax = fabs((double)x);
@@ -226,7 +234,10 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 // chunk tests then fold away; they cost about 8% at n = 4096).
 // CNT: some units may come from the per-step counter.  Without it each
 // workgroup sweeps only its own rows, with no barrier in the sweep.
-template <typename T, int NT, bool NTL, bool FULL, bool CNT>
+// RHS: a solve whose A fills all kNch chunks; B's m columns sit after them,
+// from column rhs0 = kNch * tpr * VE, as a partial extra chunk held by the
+// first ceil(m / VE) threads of each row (FULL, 256/512 threads only).
+template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS>
 __global__ void __launch_bounds__(NT)
 gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
             int k, double zero_tol, double eps_default, int det_only,
@@ -252,7 +263,11 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const int tpr = d.tpr, rsub = t / tpr, tc = t % tpr, rg = NT / tpr;
     const gptr<T> W = glb(reinterpret_cast<T *>(d.W));
     const int64_t ldw = d.ldw;
-    const int nch = (n + tpr * VE - 1) / (tpr * VE);
+    static_assert(!RHS || (FULL && kEarlyRows<NT>), "the extra chunk needs the full register layout");
+    const int nch = RHS ? kNch : (d.ncol + tpr * VE - 1) / (tpr * VE);   // chunks holding A's (and B's) columns
+    const int nrc = RHS ? (d.ncol - d.rhs0 + VE - 1) / VE : 1;   // threads of a row holding B
+    const int bcol = d.rhs0 + min(tc, nrc - 1) * VE;            // this thread's B columns (clamped)
+    const bool bown = tc < nrc;
     const gptr<BigHdr> hdr = glb(d.hdr);
     const gptr<const int32_t> rl_old = glb(static_cast<const int32_t *>(d.rowlog)) + (size_t)(k & 1) * d.mstride;
     const gptr<int32_t> rl_new = glb(d.rowlog) + (size_t)((k + 1) & 1) * d.mstride;
@@ -338,9 +353,12 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 #pragma unroll
     for (int c = 0; c < kNch; ++c)
         pw[c] = *reinterpret_cast<gptr<const VT>>(Wp + (c < nch ? c : 0) * tpr * VE + tc * VE);
+    VT pwb;
+    if constexpr (RHS) pwb = *reinterpret_cast<gptr<const VT>>(Wp + bcol);
     // (slots without a row read the pivot row, which nobody writes this step)
     T q_own = W[(int64_t)(nsr > 0 ? r0 + min(t, nsr - 1) : rp) * ldw + cp];
     VT wb[B][kNch];
+    VT wbb[B];   // RHS: the B chunk of each row slot
     const bool early = kEarlyRows<NT> && !det_only;
     if constexpr (kEarlyRows<NT>) {
         // rows not owned, the pivot row (written at step k+1) and every row
@@ -353,6 +371,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 #pragma unroll
             for (int c = 0; c < kNch; ++c)
                 wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + (c < nch ? c : 0) * tpr * VE + tc * VE));
+            if constexpr (RHS) wbb[g] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + bcol));
         }
     }
     if (rb == 0 && t == 0) {
@@ -401,6 +420,11 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
             for (int e = 0; e < VE; ++e) { ckey[c][e] = -1; prow[c][e] = (T)0; }
         }
     }
+    T prowb[VE];   // RHS: the pivot row's B columns divided by the pivot
+    if constexpr (RHS) {
+#pragma unroll
+        for (int e = 0; e < VE; ++e) prowb[e] = div_pivot_fast(vget<VT, T>(pwb, e), p, y, p_ok, slow);
+    }
     if (slow) {   // operands outside the corrected-quotient range: IEEE division
 #pragma unroll
         for (int c = 0; c < kNch; ++c)
@@ -409,6 +433,10 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 const int j = c * tpr * VE + tc * VE + e;
                 if (c < nch && j != cp) prow[c][e] = div_pivot(vget<VT, T>(pw[c], e), p, y, p_ok);
             }
+        if constexpr (RHS) {
+#pragma unroll
+            for (int e = 0; e < VE; ++e) prowb[e] = div_pivot(vget<VT, T>(pwb, e), p, y, p_ok);
+        }
     }
     if (rb == 0 && rsub == 0) {
 #pragma unroll
@@ -471,9 +499,19 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                     for (int e = 0; e < VE; ++e)
                         vset<VT, T>(wb[g][c], e,
                                     update(vget<VT, T>(wb[g][c], e), c, e, c * tpr * VE + tc * VE + e));
+            if constexpr (RHS) {   // B's columns: eqs. 14-15 as for A's, never candidates
+#pragma unroll
+                for (int e = 0; e < VE; ++e) {
+                    T cur = vget<VT, T>(wbb[g], e);
+                    if (fix) cur = div_pivot(cur, pp, yp, pp_ok);
+                    vset<VT, T>(wbb[g], e, Num<T>::fma_(-q, prowb[e], cur));
+                }
+            }
 #pragma unroll
             for (int c = 0; c < kNch; ++c)
                 if (FULL || c < nch) row_st<NTL>(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
+            if constexpr (RHS)
+                if (bown) row_st<NTL>(reinterpret_cast<gptr<VT>>(Wi + bcol), wbb[g]);
         } else {
 #pragma unroll
             for (int c = 0; c < kNch; ++c) {
@@ -506,6 +544,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 for (int c = 0; c < kNch; ++c)
                     if (all || c < nch)
                         wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + (c < nch ? c : 0) * tpr * VE + tc * VE));
+                if constexpr (RHS) wbb[g] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + bcol));
             }
         }
     };
@@ -661,8 +700,9 @@ gj_big_finish(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
     }
 }
 
-// X(i, j) = W(rowphys[collog[i]], colphys[rowlog[j]]); the last pivot row
-// still needs its eq. 14 division.  One workgroup per output row.
+// X(i, j) = W(rowphys[collog[i]], colphys[rowlog[j]]), or for a solve
+// X(i, j) = W(rowphys[collog[i]], n + j); the last pivot row still needs its
+// eq. 14 division.  One workgroup per output row.
 template <typename T>
 __global__ void __launch_bounds__(256)
 gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
@@ -678,18 +718,20 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
     const int32_t *cl = d.collog + (size_t)(n & 1) * d.mstride;
     const StepRec last = d.steps[n - 1];
     const T one = Num<T>::one();
+    const int m = d.ncol - d.rhs0;      // right-hand sides (0: inverse)
+    const int ncx = m > 0 ? m : n;      // columns of X
     for (int i = bm.y; i < n; i += d.nblk) {
         double *Xi = d.X + (int64_t)i * d.ldx;
         if (status != 0) {
-            for (int j = t; j < n; j += 256) Xi[j] = __builtin_nan("");
+            for (int j = t; j < ncx; j += 256) Xi[j] = __builtin_nan("");
             continue;
         }
         const int src = d.rowphys[cl[i]];
         const T *Ws = W + (int64_t)src * d.ldw;
         const bool fix = (src == last.rphys);
         const T pl = (T)last.p;
-        for (int j = t; j < n; j += 256) {
-            const int sc = d.colphys[rl[j]];
+        for (int j = t; j < ncx; j += 256) {
+            const int sc = m > 0 ? d.rhs0 + j : d.colphys[rl[j]];
             T x = Ws[sc];
             if (fix) x = ((sc == last.cphys) ? one : x) / pl;
             Xi[j] = (double)x;
@@ -699,7 +741,7 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int NT, bool NTL, bool FULL, bool CNT>
+template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS = false>
 static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDesc &single,
                             const int *grid_per_step,
                             int grid_init, int grid_finish, int max_n, int gather_grid,
@@ -713,7 +755,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         if (e != hipSuccess) return e;
     }
     for (int k = 0; k < max_n; ++k) {
-        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL, CNT>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
+        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL, CNT, RHS>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
                            dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only,
                            run_flag);
         e = hipGetLastError();
@@ -733,16 +775,24 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
     return e;
 }
 
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted,
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, bool rhs,
                       const BigDesc *descs, const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
                       void *const *events, const int32_t *run_flag, hipStream_t s) {
-    // the counter is compiled in for full chunks below 1024 threads only
+    // the counter is compiled in for full chunks below 1024 threads only; the
+    // extra right-hand-side chunk for FP64 full chunks below 1024 threads,
+    // without the counter
     if (counted && !(full && nt < 1024)) return hipErrorInvalidValue;
+    if (rhs && (fp32 || counted || !full || nt >= 1024)) return hipErrorInvalidValue;
 #define GJ_BIG_ARGS descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n, gather_grid, \
                     zero_tol, eps_default, det_only, events, run_flag, s
 #define GJ_BIG_CASE(TT, NTV)                                                                      \
+    if constexpr (NTV < 1024 && !std::is_same<TT, float>::value) {                                \
+        if (rhs)                                                                                  \
+            return nt_loads ? run_big_t<TT, NTV, true, true, false, true>(GJ_BIG_ARGS)            \
+                            : run_big_t<TT, NTV, false, true, false, true>(GJ_BIG_ARGS);          \
+    }                                                                                             \
     if constexpr (NTV < 1024) {                                                                   \
         if (counted)                                                                              \
             return nt_loads ? run_big_t<TT, NTV, true, true, true>(GJ_BIG_ARGS)                   \

@@ -299,6 +299,10 @@ struct BigDesc {
     const int32_t *run;   // null, or a per-matrix flag: every kernel skips it when 0
     int32_t n, R, nblk, tpr;  // order, rows per workgroup, workgroups, threads per row
     int32_t ustat;            // work units each workgroup of the step kernel takes statically
+    int32_t ncol;             // columns of W in use: n, or rhs0 + m when solving for m right-hand sides
+    int32_t rhs0;             // column of W holding B's first column (n when not solving)
+    const double *B;          // solve: right-hand sides, n x m (ldb); X receives A^-1 B (n x m, ldx)
+    int64_t ldb;
 };
 
 }  // namespace gj

@@ -30,7 +30,8 @@ def lib():
 
 def test_header_lists_the_boundary():
     names = _header_functions()
-    for f in ("gj_invert", "gj_invert_batched", "gj_det", "gj_workspace_size", "gj_status_string"):
+    for f in ("gj_invert", "gj_invert_batched", "gj_det", "gj_solve", "gj_workspace_size",
+              "gj_status_string"):
         assert f in names
 
 
@@ -71,6 +72,15 @@ def test_workspace_size(lib):
     assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 0]) == 0
     bad = gj.make_opts(precision=7)
     assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 64, None, bad) == 0
+    # solve: m passed through the host-array argument; [A | B] is swept as one array
+    sol = gj.gj_workspace_size(gj.GJ_OP_SOLVE, 4096, [16])
+    assert sol >= 4096 * (4096 + 16) * 8
+    assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 3, [1]) >= 256
+    assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 4096, [0]) == 0
+    assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 4096) == 0              # m missing
+    assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 16000, [385]) == 0      # n + m beyond 16384
+    fp32 = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED)
+    assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 100, [2], fp32) == 0   # FP64 only
 
 
 def test_argument_checks_without_gpu(lib):
@@ -89,6 +99,17 @@ def test_argument_checks_without_gpu(lib):
     assert lib.gj_invert(1000, P(1 << 30), 1000, P(1 << 40), 1000, fake, fake, fake, None, None, 0,
                          None) == gj.GJ_E_WORKSPACE
     assert lib.gj_det(0, fake, 1, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    # solve: m < 1, ldb < m, X over B, unsupported precision, missing workspace
+    A, B, X = P(1 << 30), P(1 << 34), P(1 << 38)
+    assert lib.gj_solve(8, 0, A, 8, B, 1, X, 1, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    assert lib.gj_solve(8, 2, A, 8, B, 1, X, 2, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    assert lib.gj_solve(8, 2, A, 8, B, 2, B, 2, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
+    o32 = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED)
+    assert lib.gj_solve(8, 2, A, 8, B, 2, X, 2, fake, fake, fake, ctypes.byref(o32), None, 0,
+                        None) == gj.GJ_E_UNSUPPORTED
+    assert lib.gj_solve(16000, 385, A, 16000, B, 385, X, 385, fake, fake, fake, None, None, 0,
+                        None) == gj.GJ_E_UNSUPPORTED
+    assert lib.gj_solve(8, 2, A, 8, B, 2, X, 2, fake, fake, fake, None, None, 0, None) == gj.GJ_E_WORKSPACE
     n = np.array([4, 0], dtype=np.int32)
     off = np.zeros(2, dtype=np.int64)
     assert lib.gj_invert_batched(2, n.ctypes.data_as(P), off.ctypes.data_as(P), fake, P(1 << 24),
