@@ -82,6 +82,9 @@ def _load():
             fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P, P, P,
                            ctypes.POINTER(OraResult)]
             fn.restype = ctypes.c_int
+        lib.ora_gj_invert_f64_rule.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double,
+                                               ctypes.c_int, P, P, P, ctypes.POINTER(OraResult)]
+        lib.ora_gj_invert_f64_rule.restype = ctypes.c_int
         for name in ("ora_gj_invert_f64_first_steps", "ora_gj_invert_f32_first_steps"):
             fn = getattr(lib, name)
             fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P, P, P,
@@ -121,6 +124,25 @@ def _run(fname: str, A: np.ndarray, zero_tol: float, in_dtype, out_dtype):
 def gj_invert_f64(A, zero_tol: float = -1.0):
     """FP64 in-place full-pivot GJ.  Returns (X, ipiv, jpiv, result dict)."""
     return _run("ora_gj_invert_f64", A, zero_tol, np.float64, np.float64)
+
+
+PIVOT_FULL, PIVOT_PARTIAL, PIVOT_PROGRAM = 0, 1, 2
+
+
+def gj_invert_rule_f64(A, rule: int, zero_tol: float = -1.0):
+    """FP64 in-place GJ with another pivot rule: PIVOT_PARTIAL (largest |a|
+    in column k, row swaps only) or PIVOT_PROGRAM (the section-3 program's
+    largest positive value in column k, else row k).  No preset threshold for
+    these two: with zero_tol < 0 only a zero pivot is singular."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    X = np.empty((n, n))
+    ipiv = np.full(n, -1, dtype=np.int32)
+    jpiv = np.full(n, -1, dtype=np.int32)
+    res = OraResult()
+    _load().ora_gj_invert_f64_rule(n, _ptr(A), n, float(zero_tol), int(rule), _ptr(X), _ptr(ipiv),
+                                   _ptr(jpiv), ctypes.byref(res))
+    return X, ipiv, jpiv, res.as_dict()
 
 
 def gj_invert_f32(A, zero_tol: float = 0.0):

@@ -88,6 +88,15 @@ static void ora_fill_failure(ora_result *res, int code, int rank, int n,
 }
 
 /*
+ * Pivot rules.  0: the text's rule (Obs. 2-3): largest |a| over the trailing
+ * block, ties to the first in row-major order, row and column swaps.
+ * 1: partial pivoting on |a|: largest |a| in column k, rows k..n-1, first
+ * wins; row swaps only.  2: the rule of the program in section 3: the row
+ * with the largest positive value in column k (strictly greater, starting
+ * from 0), else row k itself; row swaps only.  Rules 1 and 2 have no preset
+ * threshold (the program has none): with zero_tol < 0 only an exactly zero
+ * pivot is singular.
+ *
  * GJ_INPLACE(NAME, T, FABS, FMA, FREXP, ISFIN)
  *
  * int NAME(int n, const T *A, int64_t lda, double zero_tol,
@@ -102,11 +111,17 @@ static void ora_fill_failure(ora_result *res, int code, int rank, int n,
 #define GJ_INPLACE(NAME, T, FABS, FMA, FREXP, ISFIN, EPS_DEFAULT)                  \
 static int NAME##_run(int n, const T *A, int64_t lda, double zero_tol, T *X,       \
                       int32_t *ipiv, int32_t *jpiv, ora_result *res,               \
-                      int max_steps, double *pivots);                              \
+                      int max_steps, double *pivots, int rule);                    \
 int NAME(int n, const T *A, int64_t lda, double zero_tol, T *X,                    \
          int32_t *ipiv, int32_t *jpiv, ora_result *res)                            \
 {                                                                                  \
-    return NAME##_run(n, A, lda, zero_tol, X, ipiv, jpiv, res, n, NULL);           \
+    return NAME##_run(n, A, lda, zero_tol, X, ipiv, jpiv, res, n, NULL, 0);        \
+}                                                                                  \
+/* another pivot rule (see the rule codes above the macro)                  */   \
+int NAME##_rule(int n, const T *A, int64_t lda, double zero_tol, int rule, T *X,   \
+                int32_t *ipiv, int32_t *jpiv, ora_result *res)                     \
+{                                                                                  \
+    return NAME##_run(n, A, lda, zero_tol, X, ipiv, jpiv, res, n, NULL, rule);     \
 }                                                                                  \
 /* the first max_steps steps only, recording each pivot value; the working  */   \
 /* array is left as it stands after those steps (no depivoting)             */   \
@@ -114,11 +129,11 @@ int NAME##_first_steps(int n, const T *A, int64_t lda, double zero_tol, T *X,   
                        int32_t *ipiv, int32_t *jpiv, ora_result *res,              \
                        int max_steps, double *pivots)                              \
 {                                                                                  \
-    return NAME##_run(n, A, lda, zero_tol, X, ipiv, jpiv, res, max_steps, pivots); \
+    return NAME##_run(n, A, lda, zero_tol, X, ipiv, jpiv, res, max_steps, pivots, 0); \
 }                                                                                  \
 static int NAME##_run(int n, const T *A, int64_t lda, double zero_tol, T *X,       \
                       int32_t *ipiv, int32_t *jpiv, ora_result *res,               \
-                      int max_steps, double *pivots)                               \
+                      int max_steps, double *pivots, int rule)                     \
 {                                                                                  \
     T *W = X;                                   /* in-place working array */       \
     for (int i = 0; i < n; ++i)                                                    \
@@ -136,19 +151,35 @@ static int NAME##_run(int n, const T *A, int64_t lda, double zero_tol, T *X,    
         /* order (Obs. 2 and 3)                                               */  \
         T best = (T)-1;                                                            \
         int r = -1, c = -1, nonfinite = 0;                                         \
+        if (rule == 0) {                                                           \
         for (int i = k; i < n; ++i)                                                \
             for (int j = k; j < n; ++j) {                                          \
                 T v = FABS(W[(int64_t)i * n + j]);                                 \
                 if (!ISFIN(v)) nonfinite = 1;                                      \
                 if (v > best) { best = v; r = i; c = j; }                          \
             }                                                                      \
+        } else {   /* column k only, rows k..n-1; no column swap            */    \
+            T q = (T)0;                                                            \
+            c = k;                                                                 \
+            r = (rule == 2) ? k : -1;                                              \
+            for (int i = k; i < n; ++i) {                                          \
+                T v = W[(int64_t)i * n + k];                                       \
+                if (!ISFIN(v)) nonfinite = 1;                                      \
+                if (rule == 1) {                /* largest |a|, first wins   */    \
+                    if (FABS(v) > best) { best = FABS(v); r = i; }                 \
+                } else if (v > q) {             /* largest positive value    */    \
+                    q = v; r = i;                                                  \
+                }                                                                  \
+            }                                                                      \
+            if (rule == 2) best = FABS(W[(int64_t)r * n + k]);                     \
+        }                                                                          \
         if (nonfinite) {                                                           \
             ora_fill_failure(res, ORA_NONFINITE, k, n, ipiv, jpiv);                \
             for (int64_t t = 0; t < (int64_t)n * n; ++t) W[t] = (T)NAN;            \
             return ORA_NONFINITE;                                                  \
         }                                                                          \
-        if (k == 0 && zero_tol < 0)                                                \
-            tau = (T)n * (T)(EPS_DEFAULT) * best;   /* preset zero threshold */    \
+        if (k == 0 && zero_tol < 0)   /* preset zero threshold (none: 0) */         \
+            tau = (rule == 0) ? (T)n * (T)(EPS_DEFAULT) * best : (T)0;             \
         if (best == (T)0 || best < tau) {           /* Obs. 2: singular */         \
             ora_fill_failure(res, ORA_SINGULAR, k, n, ipiv, jpiv);                 \
             for (int64_t t = 0; t < (int64_t)n * n; ++t) W[t] = (T)NAN;            \

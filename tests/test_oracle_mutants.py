@@ -193,3 +193,74 @@ def test_solve_mutant_is_caught(tmp_path, name):
     old, new = SOLVE_MUTANTS[name]
     fn = _build_solve(tmp_path, name, old, new)
     assert _solve_battery(fn), f"mutant {name} passed every pin"
+
+
+# Planted mistakes in the other pivot rules, checked by the golden cases
+# worked by hand for each rule.
+RULE_MUTANTS = {
+    "program_rule_on_abs": ("} else if (v > q) {", "} else if (FABS(v) > q) {"),
+    "partial_rule_last_max": ("if (FABS(v) > best) { best = FABS(v); r = i; }",
+                              "if (FABS(v) >= best) { best = FABS(v); r = i; }"),
+    "partial_rule_full_threshold": ("tau = (rule == 0) ? (T)n * (T)(EPS_DEFAULT) * best : (T)0;",
+                                    "tau = (T)n * (T)(EPS_DEFAULT) * best;"),
+}
+
+
+def _build_rule(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert old in src, f"mutation anchor for {name} not found"
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(src.replace(old, new))
+    subprocess.run(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+                    "-o", str(so), str(c), "-lm"], check=True)
+    fn = ctypes.CDLL(str(so)).ora_gj_invert_f64_rule
+    P = ctypes.c_void_p
+    fn.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, ctypes.c_int, P, P, P,
+                   ctypes.POINTER(oracle.OraResult)]
+    return fn
+
+
+def _rule_battery(fn):
+    import json
+    cases = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pivot_rules.json")))["cases"]
+    failed = []
+    P = ctypes.c_void_p
+    with np.errstate(all="ignore"):
+        for case in cases:
+            A = np.ascontiguousarray(case["A"], dtype=np.float64)
+            n = A.shape[0]
+            for name, rule in (("partial", 1), ("program", 2)):
+                want = case[name]
+                X = np.empty_like(A)
+                ipiv = np.full(n, -1, np.int32)
+                jpiv = np.full(n, -1, np.int32)
+                res = oracle.OraResult()
+                fn(n, A.ctypes.data_as(P), n, -1.0, rule, X.ctypes.data_as(P),
+                   ipiv.ctypes.data_as(P), jpiv.ctypes.data_as(P), ctypes.byref(res))
+                if res.code != want["code"] or ipiv.tolist() != want["ipiv"]:
+                    failed.append(f"{case['name']}/{name}")
+        # a later pivot far below n * 2^-52 * (first pivot), but nonzero: not
+        # singular without a preset threshold
+        A = np.array([[1.0, 0.0], [0.0, 1e-300]])
+        X = np.empty_like(A)
+        ipiv = np.full(2, -1, np.int32)
+        jpiv = np.full(2, -1, np.int32)
+        res = oracle.OraResult()
+        fn(2, A.ctypes.data_as(P), 2, -1.0, 1, X.ctypes.data_as(P), ipiv.ctypes.data_as(P),
+           jpiv.ctypes.data_as(P), ctypes.byref(res))
+        if res.code != 0:
+            failed.append("tiny_pivot")
+    return failed
+
+
+def test_unmutated_rules_pass_battery(tmp_path):
+    fn = _build_rule(tmp_path, "rule_identity", "#include <math.h>", "#include <math.h>")
+    assert _rule_battery(fn) == []
+
+
+@pytest.mark.parametrize("name", sorted(RULE_MUTANTS))
+def test_rule_mutant_is_caught(tmp_path, name):
+    old, new = RULE_MUTANTS[name]
+    fn = _build_rule(tmp_path, name, old, new)
+    assert _rule_battery(fn), f"mutant {name} passed every pin"

@@ -281,6 +281,65 @@ def test_solve_columns_are_independent():
     assert X.tobytes() == np.hstack([X1, X2]).tobytes()
 
 
+RULES = {"full": 0, "partial": 1, "program": 2}
+
+
+@pytest.mark.parametrize("case", _golden("pivot_rules.json")["cases"], ids=lambda c: c["name"])
+def test_pivot_rules_golden(case):
+    A = np.array(case["A"], dtype=np.float64)
+    for name, rule in RULES.items():
+        want = case[name]
+        X, ipiv, jpiv, res = oracle.gj_invert_rule_f64(A, rule)
+        assert res["code"] == want["code"], name
+        assert ipiv.tolist() == want["ipiv"] and jpiv.tolist() == want["jpiv"], name
+        if want["code"] == 0:
+            assert res["det"] == want["det"], name
+            if "inverse" in want:
+                assert np.array_equal(X, np.array(want["inverse"])), name
+        else:
+            assert res["rank"] == want["rank"] and np.isnan(X).all(), name
+
+
+def test_partial_rule_matches_lapack_getrf():
+    """Partial pivoting on |a| picks, step by step, the rows LAPACK's getrf
+    (partial-pivoting LU) picks; no column is swapped.  The full rule with the
+    same inputs is the default entry point, bit for bit."""
+    from scipy.linalg import lu_factor
+    rng = inputs.rng_for(0, 740)
+    for _ in range(10):
+        n = int(rng.integers(2, 40))
+        A = rng.standard_normal((n, n))
+        X, ipiv, jpiv, res = oracle.gj_invert_rule_f64(A, 1)
+        _, piv = lu_factor(A)
+        assert np.array_equal(ipiv, piv) and np.array_equal(jpiv, np.arange(n))
+        assert oracle.residual(A, X) <= 10 * n * 2.0 ** -53
+        X0, i0, j0, r0 = oracle.gj_invert_rule_f64(A, 0)
+        X1, i1, j1, r1 = oracle.gj_invert_f64(A)
+        assert X0.tobytes() == X1.tobytes() and np.array_equal(i0, i1) and np.array_equal(j0, j1)
+
+
+def test_program_rule_loses_accuracy_where_max_abs_does_not():
+    """The conclusion's claim: bringing the largest |a| to the pivot position
+    reduces rounding error.  The program's rule takes the only positive entry
+    of a column however small it is: with tiny positive diagonal entries and
+    negative off-diagonal ones its pivots are tiny, the elements grow, and its
+    forward error (against the long-double run) is orders of magnitude above
+    that of either |a|-maximising rule."""
+    rng = inputs.rng_for(0, 741)
+    n = 12
+    A = -np.abs(rng.standard_normal((n, n)))
+    np.fill_diagonal(A, 1e-6)
+    Xt, _, _, rt = oracle.gj_invert_f80(A)
+    assert rt["code"] == 0
+    err = {}
+    for name, rule in RULES.items():
+        X, ipiv, _, res = oracle.gj_invert_rule_f64(A, rule)
+        assert res["code"] == 0, name
+        err[name] = np.abs(X - Xt).max() / np.abs(Xt).max()
+    assert err["full"] <= 1e-13 and err["partial"] <= 1e-13, err
+    assert err["program"] >= 1e4 * max(err["full"], err["partial"]), err
+
+
 @pytest.mark.parametrize("cond", [1e2, 1e4, 1e6])
 def test_forward_error_against_long_double(cond):
     n = 48
