@@ -76,10 +76,22 @@ enum {
 
 /* gj_opts.flags */
 enum {
-    GJ_FLAG_REUSE_PLAN = 1  /* gj_invert_batched: the workspace already holds the plan that
-                               an earlier call with the same n_host / off_host / piv_off_host
-                               and workspace uploaded; skip the upload (and the stream
-                               synchronisation it needs), e.g. while capturing a HIP graph */
+    GJ_FLAG_REUSE_PLAN = 1,   /* gj_invert_batched: the workspace already holds the plan that
+                                 an earlier call with the same n_host / off_host / piv_off_host
+                                 and workspace uploaded; skip the upload (and the stream
+                                 synchronisation it needs), e.g. while capturing a HIP graph */
+    GJ_FLAG_PIVOT_PARTIAL = 2, /* gj_invert, gj_det, gj_solve (FP64): partial pivoting on |a|
+                                 instead of the full search of Obs. 2-3: at step k the largest
+                                 |a| in column k, first row wins; rows swapped, columns never
+                                 (jpiv[k] = k) */
+    GJ_FLAG_PIVOT_PROGRAM = 4  /* as GJ_FLAG_PIVOT_PARTIAL, but with the rule of the program in
+                                 section 3: the row with the largest value greater than 0 in
+                                 column k, else row k itself (its pivot may then be zero or
+                                 negative).  With either rule a zero_tol < 0 means no preset
+                                 threshold (the program has none): only a zero pivot is
+                                 singular.  Not both; not with GJ_PREC_FP32_REFINED or
+                                 gj_invert_batched (GJ_E_UNSUPPORTED).  Every order then goes
+                                 through the streaming kernels. */
 };
 
 /* gj_workspace_size op codes */

@@ -21,6 +21,8 @@ GJ_OK, GJ_E_INVALID_ARG, GJ_E_WORKSPACE, GJ_E_HIP, GJ_E_UNSUPPORTED = 0, -1, -2,
 GJ_RES_OK, GJ_RES_SINGULAR, GJ_RES_NONFINITE, GJ_RES_REFINE_FALLBACK = 0, 1, 2, 3
 GJ_PREC_FP64, GJ_PREC_FP32_REFINED = 0, 1
 GJ_FLAG_REUSE_PLAN = 1
+GJ_FLAG_PIVOT_PARTIAL = 2   # partial pivoting on |a| (row swaps only)
+GJ_FLAG_PIVOT_PROGRAM = 4   # the section-3 program's rule: largest positive value in column k
 GJ_OP_INVERT, GJ_OP_DET, GJ_OP_INVERT_BATCHED, GJ_OP_SOLVE = 0, 1, 2, 3
 
 

@@ -30,6 +30,7 @@ struct Opts {
     int flags = 0;
     double zero_tol = -1.0;
     void *const *events = nullptr;
+    int rule = 0;   // pivot rule: 0 full, 1 partial on |a|, 2 the program's
 };
 
 bool read_opts(const gj_opts *o, Opts &out) {
@@ -38,7 +39,8 @@ bool read_opts(const gj_opts *o, Opts &out) {
     if (o->precision != GJ_PREC_FP64 && o->precision != GJ_PREC_FP32_REFINED) return false;
     if (o->want_resid != 0 && o->want_resid != 1) return false;
     if (o->max_refine_iters < 0 || o->max_refine_iters > 100) return false;
-    if (o->flags & ~GJ_FLAG_REUSE_PLAN) return false;
+    if (o->flags & ~(GJ_FLAG_REUSE_PLAN | GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM)) return false;
+    if ((o->flags & GJ_FLAG_PIVOT_PARTIAL) && (o->flags & GJ_FLAG_PIVOT_PROGRAM)) return false;
     if (std::isnan(o->zero_tol)) return false;
     out.precision = o->precision;
     out.want_resid = o->want_resid;
@@ -46,6 +48,7 @@ bool read_opts(const gj_opts *o, Opts &out) {
     out.flags = o->flags;
     out.zero_tol = o->zero_tol;
     out.events = (o->step_events[0] || o->step_events[1]) ? o->step_events : nullptr;
+    out.rule = (o->flags & GJ_FLAG_PIVOT_PARTIAL) ? 1 : (o->flags & GJ_FLAG_PIVOT_PROGRAM) ? 2 : 0;
     return true;
 }
 
@@ -359,7 +362,7 @@ size_t refined_ws(int n);
 size_t single_ws(int n, const Opts &o, bool det_only) {
     if (o.precision == GJ_PREC_FP32_REFINED) return refined_ws(n);
     size_t need = 256;
-    if (n > kOnchipMax) {
+    if (n > kOnchipMax || o.rule != 0) {
         BigShape s = big_shape(n, false, big_threads(n, false));
         need = big_bufs(s, false, 0).end;
     }
@@ -372,10 +375,10 @@ size_t single_ws(int n, const Opts &o, bool det_only) {
 // register chunks of its own row shape and B fits one more chunk, B becomes
 // that extra partial chunk and the inversion's row shape is kept (rhs);
 // otherwise [A | B] is shaped as one wider array, B right after A.
-BigShape big_shape_solve(int n, int m, bool &rhs) {
+BigShape big_shape_solve(int n, int m, int rule, bool &rhs) {
     const int nt = big_threads(n, false);
     BigShape s = big_shape(n, false, nt);
-    rhs = big_full(s, false) && nt < 1024 && m <= s.tpr * 2;
+    rhs = rule == 0 && big_full(s, false) && nt < 1024 && m <= s.tpr * 2;
     if (rhs) {
         s.rhs0 = 8 * s.tpr * 2;
         s.ncol = s.rhs0 + m;
@@ -386,23 +389,26 @@ BigShape big_shape_solve(int n, int m, bool &rhs) {
     return big_shape(n, false, big_threads(n + m, false), n + m);
 }
 
-size_t solve_ws(int n, int m) {
+size_t solve_ws(int n, int m, int rule) {
     bool rhs;
-    return big_bufs(big_shape_solve(n, m, rhs), false, 0).end;
+    return big_bufs(big_shape_solve(n, m, rule, rhs), false, 0).end;
 }
 
 gj_status run_solve(int n, int m, const double *A, int64_t lda, const double *B, int64_t ldb,
                     double *X, int64_t ldx, int32_t *ipiv, int32_t *jpiv, gj_result *res,
                     const Opts &o, void *ws, size_t ws_bytes, hipStream_t s) {
     bool rhs;
-    BigShape sh = big_shape_solve(n, m, rhs);
+    BigShape sh = big_shape_solve(n, m, o.rule, rhs);
+    if (o.rule != 0) sh.ustat = sh.share;   // the other rules are built without the counter
     BigBufs bb = big_bufs(sh, false, 0);
     if (ws_bytes < bb.end) return GJ_E_WORKSPACE;
     BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
     d.B = B;
     d.ldb = ldb;
+    d.rule = o.rule;
+    const bool full = o.rule == 0 && (rhs || big_full(sh, false));
     hipError_t e = launch_big(false, sh.nt, big_nt_loads(big_swept_bytes(sh, false)),
-                              rhs || big_full(sh, false), !rhs && big_counted(sh), rhs, nullptr,
+                              full, o.rule == 0 && !rhs && big_counted(sh), rhs, o.rule, nullptr,
                               nullptr, d, nullptr, sh.nblk, sh.nblk, n, sh.nblk, o.zero_tol,
                               kEps64, 0, o.events, nullptr, s);
     if (e != hipSuccess) return hip_fail(e);
@@ -414,7 +420,7 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
                      hipStream_t s, bool det_only) {
     const bool fp32 = (o.precision == GJ_PREC_FP32_REFINED);
     const double eps_default = fp32 ? 0.0 : kEps64;
-    if (n <= kOnchipMax) {
+    if (n <= kOnchipMax && o.rule == 0) {
         MatDesc md;
         md.a_off = 0;
         md.x_off = 0;
@@ -439,11 +445,14 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
     }
     const int nt = big_threads(n, fp32);
     BigShape sh = big_shape(n, fp32, nt);
+    if (o.rule != 0) sh.ustat = sh.share;   // the other rules are built without the counter
     BigBufs bb = big_bufs(sh, fp32, 0);
     if (ws_bytes < bb.end) return GJ_E_WORKSPACE;
     BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
-    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32), big_counted(sh), false,
-                              nullptr, nullptr,
+    d.rule = o.rule;
+    hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)),
+                              o.rule == 0 && big_full(sh, fp32), o.rule == 0 && big_counted(sh),
+                              false, o.rule, nullptr, nullptr,
                               d, nullptr, sh.nblk, sh.nblk, n,
                               det_only ? 0 : sh.nblk, o.zero_tol, eps_default, det_only ? 1 : 0,
                               o.events, nullptr, s);
@@ -533,7 +542,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, true, nt);
         BigBufs bb = big_bufs(sh, true, L.big32);
         d32 = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true), big_counted(sh), false,
+        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true), big_counted(sh), false, 0,
                           nullptr, nullptr, d32,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, 0.0, 0.0, det_only ? 1 : 0, o.events, nullptr, s));
@@ -597,7 +606,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, false, nt);
         BigBufs bb = big_bufs(sh, false, L.over64);
         BigDesc d = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false), big_counted(sh), false,
+        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false), big_counted(sh), false, 0,
                           nullptr, nullptr, d,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
@@ -1056,7 +1065,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)E.bmap.size();
-        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full, E.big_counted, false,
+        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full, E.big_counted, false, 0,
                           reinterpret_cast<const BigDesc *>(w + E.off_descs),
                           reinterpret_cast<const int2 *>(w + E.off_bmap), BigDesc(),
                           E.grid_per_step.data(), nb, nb, E.big_max_n, nb, 0.0, 0.0, 0, o.events,
@@ -1083,7 +1092,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)P.fb_bmap.size();
-        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full, P.fb_counted, false,
+        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full, P.fb_counted, false, 0,
                           reinterpret_cast<const BigDesc *>(w + P.off_fb_descs),
                           reinterpret_cast<const int2 *>(w + P.off_fb_bmap), BigDesc(),
                           P.fb_grid.data(), nb, nb, E.big_max_n, nb, o.zero_tol, kEps64, 0, nullptr,
@@ -1190,15 +1199,16 @@ size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
     if (!read_opts(opts, o)) return 0;
     if (op == GJ_OP_INVERT || op == GJ_OP_DET) {
         if (n_or_batch < 1 || n_or_batch > kMaxN) return 0;
+        if (o.rule != 0 && o.precision != GJ_PREC_FP64) return 0;
         return single_ws(n_or_batch, o, op == GJ_OP_DET);
     }
     if (op == GJ_OP_SOLVE) {
         if (n_or_batch < 1 || !n_host || n_host[0] < 1 || n_or_batch + n_host[0] > kMaxN) return 0;
         if (o.precision != GJ_PREC_FP64 || o.want_resid) return 0;
-        return solve_ws(n_or_batch, n_host[0]);
+        return solve_ws(n_or_batch, n_host[0], o.rule);
     }
     if (op == GJ_OP_INVERT_BATCHED) {
-        if (n_or_batch < 1 || !n_host) return 0;
+        if (n_or_batch < 1 || !n_host || o.rule != 0) return 0;
         if (o.precision == GJ_PREC_FP32_REFINED) {
             RefBatchPlan R;
             if (!plan_refined_batch(n_or_batch, n_host, R)) return 0;
@@ -1212,7 +1222,8 @@ size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
 }
 
 static bool needs_ws(int n, const Opts &o, bool det_only) {
-    return n > kOnchipMax || o.precision == GJ_PREC_FP32_REFINED || (o.want_resid && !det_only);
+    return n > kOnchipMax || o.rule != 0 || o.precision == GJ_PREC_FP32_REFINED ||
+           (o.want_resid && !det_only);
 }
 
 gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t ldx,
@@ -1223,7 +1234,7 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
         if (!read_opts(opts, o)) return GJ_E_INVALID_ARG;
         if (n < 1 || lda < n || ldx < n || !A || !X || !ipiv || !jpiv || !res)
             return GJ_E_INVALID_ARG;
-        if (n > kMaxN) return GJ_E_UNSUPPORTED;
+        if (n > kMaxN || (o.rule != 0 && o.precision != GJ_PREC_FP64)) return GJ_E_UNSUPPORTED;
         const size_t abytes = ((size_t)(n - 1) * lda + n) * 8, xbytes = ((size_t)(n - 1) * ldx + n) * 8;
         if (overlaps(A, abytes, X, xbytes)) return GJ_E_INVALID_ARG;
         const size_t need = single_ws(n, o, false);
@@ -1239,7 +1250,8 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
         gj_status st = run_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes, s, false);
         if (st != GJ_OK || !o.want_resid) return st;
         size_t off = 0;
-        if (n > kOnchipMax) off = a256(big_bufs(big_shape(n, false, big_threads(n, false)), false, 0).end);
+        if (n > kOnchipMax || o.rule != 0)
+            off = a256(big_bufs(big_shape(n, false, big_threads(n, false)), false, 0).end);
         return run_resid(n, A, lda, X, ldx, res, (char *)ws + off, s);
     } catch (...) {
         return GJ_E_HIP;
@@ -1252,7 +1264,7 @@ gj_status gj_det(int32_t n, const double *A, int64_t lda, int32_t *ipiv, int32_t
         Opts o;
         if (!read_opts(opts, o)) return GJ_E_INVALID_ARG;
         if (n < 1 || lda < n || !A || !ipiv || !jpiv || !res) return GJ_E_INVALID_ARG;
-        if (n > kMaxN) return GJ_E_UNSUPPORTED;
+        if (n > kMaxN || (o.rule != 0 && o.precision != GJ_PREC_FP64)) return GJ_E_UNSUPPORTED;
         const size_t need = single_ws(n, o, true);
         if (needs_ws(n, o, true)) {
             if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
@@ -1282,7 +1294,7 @@ gj_status gj_solve(int32_t n, int32_t m, const double *A, int64_t lda, const dou
         const size_t bbytes = ((size_t)(n - 1) * ldb + m) * 8, xbytes = ((size_t)(n - 1) * ldx + m) * 8;
         if (overlaps(A, abytes, X, xbytes) || overlaps(B, bbytes, X, xbytes)) return GJ_E_INVALID_ARG;
         if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
-        if (ws_bytes < solve_ws(n, m)) return GJ_E_WORKSPACE;
+        if (ws_bytes < solve_ws(n, m, o.rule)) return GJ_E_WORKSPACE;
         if (overlaps(ws, ws_bytes, X, xbytes) || overlaps(ws, ws_bytes, A, abytes) ||
             overlaps(ws, ws_bytes, B, bbytes))
             return GJ_E_INVALID_ARG;
@@ -1303,6 +1315,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         if (batch < 1 || !n_host || !off_host || !piv_off_host || !A || !X || !ipiv || !jpiv ||
             !res)
             return GJ_E_INVALID_ARG;
+        if (o.rule != 0) return GJ_E_UNSUPPORTED;   // the batch kernels search the full block
         if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
         for (int b = 0; b < batch; ++b)
             if (n_host[b] < 1 || n_host[b] > kMaxN || off_host[b] < 0 || piv_off_host[b] < 0)
@@ -1375,7 +1388,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         }
         if (!P.big_members.empty()) {
             const int nb = (int)P.bmap.size();
-            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full, P.big_counted, false,
+            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full, P.big_counted, false, 0,
                                       reinterpret_cast<const BigDesc *>(w + P.off_descs),
                                       reinterpret_cast<const int2 *>(w + P.off_bmap), BigDesc(),
                                       P.grid_per_step.data(), nb, nb, P.big_max_n, nb, o.zero_tol,

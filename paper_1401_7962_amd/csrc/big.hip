@@ -31,6 +31,10 @@
 //     needed.
 //   * The final depivoting (Obs. 3) is a gather:
 //       X(i, j) = W(rowphys[collog[i]], colphys[rowlog[j]]).
+//   * Other pivot rules (d.rule): 1 partial pivoting on |a| (largest |a| in
+//     the next column), 2 the rule of the program in section 3 (the row with
+//     the largest positive value in the next column, else the next row).
+//     Both only restrict the candidates to one column; no column moves.
 //   * Solving A X = B runs the same elimination on [A | B] (eq. 2 with
 //     D^0 = B): the m columns of B follow A's columns in W (from column
 //     rhs0: n, or the end of A's last register chunk), get the same eq. 14-15
@@ -208,9 +212,15 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
             if (j < n) {
                 x = (T)d.A[(int64_t)i * d.lda + j];
                 const double ax = fabs((double)x);
-                nf |= !(ax <= 1.7976931348623157e308);
+                // candidates: the whole matrix, or column 0 for the other
+                // rules; the program's rule scores the value itself and takes
+                // row 0 (score 0) when nothing in the column is positive
+                const bool incol = d.rule == 0 || j == 0;
+                nf |= incol && !(ax <= 1.7976931348623157e308);
+                const double sc = d.rule == 2 ? (x > (T)0 ? (double)x : 0.0) : ax;
+                const bool cand = incol && (d.rule != 2 || x > (T)0 || i == 0);
                 const uint32_t key = ((uint32_t)i << 16) | (uint32_t)j;
-                if (better(ax, key, ba, bk)) { ba = ax; bv = (double)x; bk = key; bi = i; bj = j; }
+                if (cand && better(sc, key, ba, bk)) { ba = sc; bv = (double)x; bk = key; bi = i; bj = j; }
             }
             W[(int64_t)i * d.ldw + j] = x;
         }
@@ -234,10 +244,12 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 // chunk tests then fold away; they cost about 8% at n = 4096).
 // CNT: some units may come from the per-step counter.  Without it each
 // workgroup sweeps only its own rows, with no barrier in the sweep.
+// RULE: the pivot rule (d.rule); 1 and 2 restrict the candidates to the
+// next column, 2 scores the signed value.
 // RHS: a solve whose A fills all kNch chunks; B's m columns sit after them,
 // from column rhs0 = kNch * tpr * VE, as a partial extra chunk held by the
 // first ceil(m / VE) threads of each row (FULL, 256/512 threads only).
-template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS>
+template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS, int RULE>
 __global__ void __launch_bounds__(NT)
 gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
             int k, double zero_tol, double eps_default, int det_only,
@@ -326,7 +338,10 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     block_argmax<NT>(pa, pv, pk, pi, pj, s_a, s_v, s_k, s_i, s_j);
     double tau;
     if (k == 0) {
-        tau = (zero_tol >= 0.0) ? (double)(T)zero_tol : (double)((T)n * (T)eps_default * (T)pa);
+        // preset threshold: n eps max|a| for the text's rule, none (0) for the
+        // others (the program has none)
+        tau = (zero_tol >= 0.0) ? (double)(T)zero_tol
+                                : (RULE == 0 ? (double)((T)n * (T)eps_default * (T)pa) : 0.0);
         if (rb == 0 && t == 0) hdr->tau = tau;
     } else {
         tau = tau_prev;
@@ -334,7 +349,8 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const bool stop_nf = !(pa <= 1.7976931348623157e308);
     // (a winner without a position cannot occur for k < n; refusing it keeps
     // every later index in bounds)
-    const bool stop_sing = (pa == 0.0) || ((T)pa < (T)tau) || pi < 0 || pj < 0;
+    const double apv = fabs(pv);   // |pivot| (the winner's score is |pv| for RULE < 2)
+    const bool stop_sing = (apv == 0.0) || ((T)apv < (T)tau) || pi < 0 || pj < 0;
     if (stop_nf || stop_sing) {
         if (rb == 0 && t == 0) {
             hdr->status = stop_nf ? GJ_RES_NONFINITE : GJ_RES_SINGULAR;
@@ -451,6 +467,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 
     // ---- 4. eq. 15 on the swept rows + fused pivot search for step k+1
     T bvT = (T)0;                 // running best (signed), "no candidate": (0, key 0xFFFFFFFF)
+    T bsT = (T)-1;                // RULE 2: the best's score (-1: no candidate)
     uint32_t bk = 0xFFFFFFFFu;
     int bi = -1, bj = -1;
     bool nf = false;
@@ -466,11 +483,20 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
             cur = (j == cp) ? (T)0 : cur;
             const T nv = Num<T>::fma_(-q, prow[c][e], cur);
             const int cl = ckey[c][e];
-            const bool cand = rcand & (cl > k);   // '&', '|': no short-circuit branches
-            const T an = Num<T>::abs_(nv), ab = Num<T>::abs_(bvT);   // in T: exact
+            // '&', '|': no short-circuit branches
+            const bool cand = rcand & (RULE == 0 ? (cl > k) : (cl == k + 1));
+            const T an = Num<T>::abs_(nv);
             nf |= cand & !Num<T>::finite_(an);
             const uint32_t key = rkey | (uint32_t)cl;
-            const bool upd = cand & ((an > ab) | ((an == ab) & (key < bk)));
+            bool upd;
+            if constexpr (RULE == 2) {   // largest positive value, else the next row (score 0)
+                const T sc = (nv > (T)0) ? nv : ((rn == k + 1) ? (T)0 : (T)-1);
+                upd = cand & (sc >= (T)0) & ((sc > bsT) | ((sc == bsT) & (key < bk)));
+                bsT = upd ? sc : bsT;
+            } else {
+                const T ab = Num<T>::abs_(bvT);   // in T: exact
+                upd = cand & ((an > ab) | ((an == ab) & (key < bk)));
+            }
             bvT = upd ? nv : bvT;
             bk = upd ? key : bk;
             bi = upd ? i : bi;
@@ -637,7 +663,9 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     }
     if (k + 1 < n) {
         const int any_nf = __syncthreads_or(nf ? 1 : 0);
-        double bv = (double)bvT, ba = fabs(bv);
+        // (the reductions compare |a|: RULE 2's "no candidate" score -1 goes
+        // out as 0 with key 0xFFFFFFFF, below every real candidate)
+        double bv = (double)bvT, ba = (RULE == 2) ? fmax((double)bsT, 0.0) : fabs(bv);
         block_argmax<NT>(ba, bv, bk, bi, bj, s_a, s_v, s_k, s_i, s_j);
         if (t == 0) {
             BigPart o;
@@ -741,7 +769,7 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS = false>
+template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS = false, int RULE = 0>
 static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDesc &single,
                             const int *grid_per_step,
                             int grid_init, int grid_finish, int max_n, int gather_grid,
@@ -755,7 +783,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         if (e != hipSuccess) return e;
     }
     for (int k = 0; k < max_n; ++k) {
-        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL, CNT, RHS>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
+        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL, CNT, RHS, RULE>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
                            dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only,
                            run_flag);
         e = hipGetLastError();
@@ -775,7 +803,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
     return e;
 }
 
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, bool rhs,
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, bool rhs, int rule,
                       const BigDesc *descs, const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
@@ -785,9 +813,19 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted,
     // without the counter
     if (counted && !(full && nt < 1024)) return hipErrorInvalidValue;
     if (rhs && (fp32 || counted || !full || nt >= 1024)) return hipErrorInvalidValue;
+    // the other pivot rules: FP64, per-chunk tests, no counter, B right after A
+    if (rule != 0 && (fp32 || counted || full || rhs || rule > 2)) return hipErrorInvalidValue;
 #define GJ_BIG_ARGS descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n, gather_grid, \
                     zero_tol, eps_default, det_only, events, run_flag, s
 #define GJ_BIG_CASE(TT, NTV)                                                                      \
+    if constexpr (!std::is_same<TT, float>::value) {                                              \
+        if (rule == 1)                                                                            \
+            return nt_loads ? run_big_t<TT, NTV, true, false, false, false, 1>(GJ_BIG_ARGS)       \
+                            : run_big_t<TT, NTV, false, false, false, false, 1>(GJ_BIG_ARGS);     \
+        if (rule == 2)                                                                            \
+            return nt_loads ? run_big_t<TT, NTV, true, false, false, false, 2>(GJ_BIG_ARGS)       \
+                            : run_big_t<TT, NTV, false, false, false, false, 2>(GJ_BIG_ARGS);     \
+    }                                                                                             \
     if constexpr (NTV < 1024 && !std::is_same<TT, float>::value) {                                \
         if (rhs)                                                                                  \
             return nt_loads ? run_big_t<TT, NTV, true, true, false, true>(GJ_BIG_ARGS)            \

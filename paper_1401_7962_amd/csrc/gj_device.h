@@ -301,6 +301,7 @@ struct BigDesc {
     int32_t ustat;            // work units each workgroup of the step kernel takes statically
     int32_t ncol;             // columns of W in use: n, or rhs0 + m when solving for m right-hand sides
     int32_t rhs0;             // column of W holding B's first column (n when not solving)
+    int32_t rule;             // pivot rule: 0 full (Obs. 2-3), 1 partial on |a|, 2 the program's (section 3)
     const double *B;          // solve: right-hand sides, n x m (ldb); X receives A^-1 B (n x m, ldx)
     int64_t ldb;
 };

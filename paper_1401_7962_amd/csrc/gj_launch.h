@@ -31,8 +31,11 @@ hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks
 // nontemporal row loads; full: every matrix uses all register chunks;
 // counted: some descriptor leaves work units to the per-step counter
 // (needs full and nt < 1024); rhs: a solve whose B is an extra partial
-// register chunk after A's full ones (FP64, full, nt < 1024, not counted).
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, bool rhs, const BigDesc *descs,
+// register chunk after A's full ones (FP64, full, nt < 1024, not counted);
+// rule: pivot rule of every descriptor (0 full; 1, 2 need FP64 and none of
+// full, counted, rhs).
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, bool rhs, int rule,
+                      const BigDesc *descs,
                       const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init,
                       int grid_finish, int max_n, int gather_grid, double zero_tol,

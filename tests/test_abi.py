@@ -81,6 +81,17 @@ def test_workspace_size(lib):
     assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 16000, [385]) == 0      # n + m beyond 16384
     fp32 = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED)
     assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 100, [2], fp32) == 0   # FP64 only
+    # pivot rules: every order through the streaming kernels; FP64, single matrix only
+    part = gj.make_opts(flags=gj.GJ_FLAG_PIVOT_PARTIAL)
+    prog = gj.make_opts(flags=gj.GJ_FLAG_PIVOT_PROGRAM)
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 64, None, part) > 64 * 64 * 8
+    assert gj.gj_workspace_size(gj.GJ_OP_DET, 64, None, prog) > 64 * 64 * 8
+    assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 64, [3], prog) > 64 * 67 * 8
+    both = gj.make_opts(flags=gj.GJ_FLAG_PIVOT_PARTIAL | gj.GJ_FLAG_PIVOT_PROGRAM)
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 64, None, both) == 0
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 9], part) == 0
+    p32 = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_PIVOT_PARTIAL)
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None, p32) == 0
 
 
 def test_argument_checks_without_gpu(lib):
@@ -110,6 +121,21 @@ def test_argument_checks_without_gpu(lib):
     assert lib.gj_solve(16000, 385, A, 16000, B, 385, X, 385, fake, fake, fake, None, None, 0,
                         None) == gj.GJ_E_UNSUPPORTED
     assert lib.gj_solve(8, 2, A, 8, B, 2, X, 2, fake, fake, fake, None, None, 0, None) == gj.GJ_E_WORKSPACE
+    # pivot rules: not both, not refined, not batched; a small order then needs a workspace
+    both = gj.make_opts(flags=gj.GJ_FLAG_PIVOT_PARTIAL | gj.GJ_FLAG_PIVOT_PROGRAM)
+    assert lib.gj_invert(8, A, 8, X, 8, fake, fake, fake, ctypes.byref(both), None, 0,
+                         None) == gj.GJ_E_INVALID_ARG
+    p32 = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_PIVOT_PROGRAM)
+    assert lib.gj_invert(8, A, 8, X, 8, fake, fake, fake, ctypes.byref(p32), None, 0,
+                         None) == gj.GJ_E_UNSUPPORTED
+    part = gj.make_opts(flags=gj.GJ_FLAG_PIVOT_PARTIAL)
+    assert lib.gj_invert(8, A, 8, X, 8, fake, fake, fake, ctypes.byref(part), None, 0,
+                         None) == gj.GJ_E_WORKSPACE
+    nb = np.array([4, 5], dtype=np.int32)
+    ob = np.array([0, 16], dtype=np.int64)
+    assert lib.gj_invert_batched(2, nb.ctypes.data_as(P), ob.ctypes.data_as(P), A, X,
+                                 ob.ctypes.data_as(P), fake, fake, fake, ctypes.byref(part),
+                                 P(1 << 28), 1 << 20, None) == gj.GJ_E_UNSUPPORTED
     n = np.array([4, 0], dtype=np.int32)
     off = np.zeros(2, dtype=np.int64)
     assert lib.gj_invert_batched(2, n.ctypes.data_as(P), off.ctypes.data_as(P), fake, P(1 << 24),
