@@ -377,6 +377,42 @@ def bench_solve(n: int = 4096, m: int = 16, reps: int = 3):
             "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def bench_pivot_rules(n: int = 4096, n_growth: int = 512, reps: int = 2):
+    """The three pivot rules on the GPU: time per inversion of the headline
+    input, and the normwise residual ||A X - I||_F / (||A||_F ||X||_F) on a
+    matrix where the program's signed rule takes tiny pivots (negative
+    off-diagonal entries, a tiny positive diagonal)."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    A = torch.from_numpy(inputs.single_dominant(n)).to("cuda")
+    rng = inputs.rng_for(0, 4343)
+    G = -np.abs(rng.standard_normal((n_growth, n_growth)))
+    np.fill_diagonal(G, 1e-6)
+    G = torch.from_numpy(G).to("cuda")
+    stream = torch.cuda.current_stream()
+    out = {"n": n, "growth_n": n_growth}
+    for name, flags in (("full", 0), ("partial", gj.GJ_FLAG_PIVOT_PARTIAL),
+                        ("program", gj.GJ_FLAG_PIVOT_PROGRAM)):
+        o = gj.make_opts(flags=flags)
+        X, ip, jp, res = gj.gj_invert(A, opts=o)
+        torch.cuda.synchronize()
+        e = _events(2 * reps, stream)
+        for k in range(reps):
+            e[2 * k].record()
+            gj.gj_invert(A, X, ip, jp, res, o)
+            e[2 * k + 1].record()
+        torch.cuda.synchronize()
+        ms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+        Xg, _, _, rg = gj.gj_invert(G, opts=o)
+        torch.cuda.synchronize()
+        code = gj.results_to_dicts(rg)[0]["code"]
+        resid = float(torch.linalg.norm(G @ Xg - torch.eye(n_growth, dtype=torch.float64, device="cuda"))
+                      / (torch.linalg.norm(G) * torch.linalg.norm(Xg)))
+        out[name] = {"ms": round(ms, 1), "growth_case_code": code, "growth_case_resid": resid}
+    return out
+
+
 def ctypes_ptr(event):
     """hipEvent_t handle of a torch.cuda.Event."""
     return event.cuda_event
@@ -408,7 +444,8 @@ LEGS = {"latency_small": lambda: bench_latency_small(),
         "batch_uneven_100k": lambda: bench_batch_uneven(),
         "conditioned_8192": lambda: bench_conditioned_8192(),
         "batch_conditioned_20k": lambda: bench_batch_conditioned(),
-        "solve_4096": lambda: bench_solve()}
+        "solve_4096": lambda: bench_solve(),
+        "pivot_rules": lambda: bench_pivot_rules()}
 
 
 def main():
@@ -496,6 +533,9 @@ def main():
         torch.cuda.empty_cache()
         extras["solve_4096"] = bench_solve()
         print("bench: solve done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["pivot_rules"] = bench_pivot_rules()
+        print("bench: pivot rules done", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["extras"] = extras
     if not args.no_cpu_baseline:
