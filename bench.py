@@ -205,8 +205,10 @@ def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
         lu_ref[idx] = torch.linalg.slogdet(M)[1].cpu().numpy()
         del M, base
     Xs = {}
-    for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
-        opts = gj.make_opts(precision=prec)
+    for name, prec, flags in (("plain_fp64", gj.GJ_PREC_FP64, 0),
+                              ("fp32_refined", gj.GJ_PREC_FP32_REFINED, 0),
+                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE)):
+        opts = gj.make_opts(precision=prec, flags=flags)
         X = torch.empty_like(A)
         ip = torch.empty(int(sizes.sum()), dtype=torch.int32, device="cuda")
         jp = torch.empty_like(ip)
@@ -289,8 +291,10 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
            "closed_form_logabsdet": inputs.closed_form_logdet(n, 1e6)}
     Xs = {}
     stream = torch.cuda.current_stream()
-    for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
-        opts = gj.make_opts(precision=prec)
+    for name, prec, flags in (("plain_fp64", gj.GJ_PREC_FP64, 0),
+                              ("fp32_refined", gj.GJ_PREC_FP32_REFINED, 0),
+                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE)):
+        opts = gj.make_opts(precision=prec, flags=flags)
         X = torch.empty_like(A)
         ip = torch.empty(n, dtype=torch.int32, device="cuda")
         jp = torch.empty_like(ip)
@@ -317,6 +321,9 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
         Xs[name] = X
     d = float(torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"]))
     out["refined_vs_plain_rel_frobenius"] = d
+    out["accurate_vs_refined_rel_frobenius"] = float(
+        torch.linalg.norm(Xs["fp32_refined_accurate"] - Xs["fp32_refined"]) / torch.linalg.norm(Xs["fp32_refined"]))
+    out["speedup_accurate_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined_accurate"]["ms"], 3)
     out["speedup_refined_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined"]["ms"], 3)
     # roofline of the refinement's dominant kernel: the Newton-Schulz product
     # X R (n x n x n, FP64 MFMA), timed alone with HIP events
@@ -413,6 +420,47 @@ def bench_pivot_rules(n: int = 4096, n_growth: int = 512, reps: int = 2):
     return out
 
 
+def bench_accuracy_exact(n: int = 4096, span: int = 20, reps: int = 2):
+    """Forward error against an exactly known inverse at the headline order:
+    A = H D H^T with H Sylvester-Hadamard and D a diagonal of powers of two
+    spanning 2^span (cond(A) = 2^span); A and A^-1 = H D^-1 H^T / n^2 are
+    exact in FP64 (integer and dyadic sums below 2^53).  Plain FP64
+    elimination, FP32 + FP64 Newton-Schulz, and the same with the
+    accurate-residual updates."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    H = torch.from_numpy(inputs.sylvester_hadamard(n)).to("cuda")
+    rng = inputs.rng_for(0, 4444)
+    e = rng.integers(0, span + 1, size=n)
+    e[0], e[1] = 0, span
+    d = torch.from_numpy(np.ldexp(1.0, e)).to("cuda")
+    A = (H * d) @ H.T
+    Ainv = (H / d) @ H.T / float(n * n)
+    del H
+    stream = torch.cuda.current_stream()
+    out = {"n": n, "cond": 2.0 ** span}
+    for name, prec, flags in (("plain_fp64", gj.GJ_PREC_FP64, 0),
+                              ("fp32_refined", gj.GJ_PREC_FP32_REFINED, 0),
+                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE)):
+        o = gj.make_opts(precision=prec, flags=flags)
+        X, ip, jp, res = gj.gj_invert(A, opts=o)
+        torch.cuda.synchronize()
+        ev = _events(2 * reps, stream)
+        for k in range(reps):
+            ev[2 * k].record()
+            gj.gj_invert(A, X, ip, jp, res, o)
+            ev[2 * k + 1].record()
+        torch.cuda.synchronize()
+        ms = min(ev[2 * k].elapsed_time(ev[2 * k + 1]) for k in range(reps))
+        r = gj.results_to_dicts(res)[0]
+        err = float(torch.linalg.norm(X - Ainv) / torch.linalg.norm(Ainv))
+        out[name] = {"ms": round(ms, 1), "code": r["code"], "refine_iters": r["refine_iters"],
+                     "rel_forward_error": err}
+        del X
+    return out
+
+
 def ctypes_ptr(event):
     """hipEvent_t handle of a torch.cuda.Event."""
     return event.cuda_event
@@ -445,7 +493,8 @@ LEGS = {"latency_small": lambda: bench_latency_small(),
         "conditioned_8192": lambda: bench_conditioned_8192(),
         "batch_conditioned_20k": lambda: bench_batch_conditioned(),
         "solve_4096": lambda: bench_solve(),
-        "pivot_rules": lambda: bench_pivot_rules()}
+        "pivot_rules": lambda: bench_pivot_rules(),
+        "accuracy_exact_4096": lambda: bench_accuracy_exact()}
 
 
 def main():
@@ -536,6 +585,9 @@ def main():
         torch.cuda.empty_cache()
         extras["pivot_rules"] = bench_pivot_rules()
         print("bench: pivot rules done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["accuracy_exact_4096"] = bench_accuracy_exact()
+        print("bench: exact-inverse accuracy done", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["extras"] = extras
     if not args.no_cpu_baseline:

@@ -84,7 +84,7 @@ enum {
                                  instead of the full search of Obs. 2-3: at step k the largest
                                  |a| in column k, first row wins; rows swapped, columns never
                                  (jpiv[k] = k) */
-    GJ_FLAG_PIVOT_PROGRAM = 4  /* as GJ_FLAG_PIVOT_PARTIAL, but with the rule of the program in
+    GJ_FLAG_PIVOT_PROGRAM = 4, /* as GJ_FLAG_PIVOT_PARTIAL, but with the rule of the program in
                                  section 3: the row with the largest value greater than 0 in
                                  column k, else row k itself (its pivot may then be zero or
                                  negative).  With either rule a zero_tol < 0 means no preset
@@ -92,6 +92,14 @@ enum {
                                  singular.  Not both; not with GJ_PREC_FP32_REFINED or
                                  gj_invert_batched (GJ_E_UNSUPPORTED).  Every order then goes
                                  through the streaming kernels. */
+    GJ_FLAG_ACCURATE = 8      /* GJ_PREC_FP32_REFINED only (else GJ_E_INVALID_ARG), gj_invert
+                                 (gj_invert_batched: GJ_E_UNSUPPORTED): after the FP64
+                                 Newton-Schulz loop, up to 2 more updates with residuals
+                                 I - A X formed from error-free split products on the FP64
+                                 matrix cores, while ||I - A X||_F at least halves.  The FP64
+                                 residual stalls at about n u cond(A); these bring the forward
+                                 error of X to about u.  gj_result.refine_iters counts all
+                                 updates kept.  The workspace grows by 6 n^2 doubles. */
 };
 
 /* gj_workspace_size op codes */

@@ -39,7 +39,9 @@ bool read_opts(const gj_opts *o, Opts &out) {
     if (o->precision != GJ_PREC_FP64 && o->precision != GJ_PREC_FP32_REFINED) return false;
     if (o->want_resid != 0 && o->want_resid != 1) return false;
     if (o->max_refine_iters < 0 || o->max_refine_iters > 100) return false;
-    if (o->flags & ~(GJ_FLAG_REUSE_PLAN | GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM)) return false;
+    if (o->flags & ~(GJ_FLAG_REUSE_PLAN | GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM | GJ_FLAG_ACCURATE))
+        return false;
+    if ((o->flags & GJ_FLAG_ACCURATE) && o->precision != GJ_PREC_FP32_REFINED) return false;
     if ((o->flags & GJ_FLAG_PIVOT_PARTIAL) && (o->flags & GJ_FLAG_PIVOT_PROGRAM)) return false;
     if (std::isnan(o->zero_tol)) return false;
     out.precision = o->precision;
@@ -357,10 +359,11 @@ bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
 
 size_t resid_ws(int n);
 struct RefinedLayout;
-size_t refined_ws(int n);
+size_t refined_ws(int n, bool acc);
 
 size_t single_ws(int n, const Opts &o, bool det_only) {
-    if (o.precision == GJ_PREC_FP32_REFINED) return refined_ws(n);
+    if (o.precision == GJ_PREC_FP32_REFINED)
+        return refined_ws(n, (o.flags & GJ_FLAG_ACCURATE) && !det_only);
     size_t need = 256;
     if (n > kOnchipMax || o.rule != 0) {
         BigShape s = big_shape(n, false, big_threads(n, false));
@@ -465,13 +468,20 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
 constexpr int kDetBlock = 128;          // diagonal blocks of the FP64 determinant
 constexpr double kAcceptResid = 1e-2;   // ||I - A X||_F above this: fall back to FP64
 constexpr double kStall = 0.5;          // an update must at least halve ||R||_F
+// accurate-residual phase: slices of 19 bits keep every partial sum of the
+// exact products below 2^53 units for n <= 16384; at most 2 updates (from an
+// accepted FP64 iterate with residual R_0 they leave an error of about
+// ||R_0||^4 + u; a third residual only confirmed the floor in every case
+// measured, at 8 products of n^3)
+constexpr int kAccBeta = 19;
+constexpr int kAccIters = 2;
 
 struct RefinedLayout {
-    size_t ctl, big32, xw, r, over64, t, dinv, part_r, part_a, part_x, blockres, rows, cols, bpiv, end;
+    size_t ctl, big32, xw, r, over64, t, dinv, part_r, part_a, part_x, blockres, rows, cols, bpiv, acc, end;
     int nparts;
 };
 
-RefinedLayout refined_layout(int n) {
+RefinedLayout refined_layout(int n, bool acc = false) {
     RefinedLayout L;
     size_t c = 0;
     const size_t n2 = (size_t)n * n * 8;
@@ -502,6 +512,9 @@ RefinedLayout refined_layout(int n) {
     L.rows = c; c = a256(c + (size_t)n * 4);
     L.cols = c; c = a256(c + (size_t)n * 4);
     L.bpiv = c; c = a256(c + 2 * kDetBlock * 4);
+    // accurate-residual phase: three slices of A and three of X
+    L.acc = c;
+    if (acc) c = a256(c + 6 * n2);
     L.end = c;
     return L;
 }
@@ -512,7 +525,8 @@ RefinedLayout refined_layout(int n) {
 gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int64_t ldx,
                              int32_t *ipiv, int32_t *jpiv, gj_result *res, const Opts &o, char *w,
                              hipStream_t s, bool det_only) {
-    const RefinedLayout L = refined_layout(n);
+    const bool acc = (o.flags & GJ_FLAG_ACCURATE) && !det_only;
+    const RefinedLayout L = refined_layout(n, acc);
     void *ctl = w + L.ctl;
     double *Xw = reinterpret_cast<double *>(w + L.xw);
     double *R = reinterpret_cast<double *>(w + L.r);
@@ -591,6 +605,48 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         }
         GJ_TRY(launch_refine_finish(ctl, 1, kAcceptResid, 1, s));
         GJ_TRY(launch_copy_back(nullptr, m, ctl, 1, row_blocks, s));
+        if (acc) {
+            // accurate residuals (error-free split products on the matrix
+            // cores) for a few more updates; skipped when the FP64 result
+            // falls back.  Buffers: R for the residual, Xw for the update.
+            const size_t nn = (size_t)n * n;
+            double *As = reinterpret_cast<double *>(w + L.acc), *Xs = As + 3 * nn;
+            GJ_TRY(launch_acc_prepare(ctl, 1, s));
+            const int32_t *ra = ctl_run_acc(ctl);
+            GJ_TRY(launch_slice_rows(A, lda, n, As, kAccBeta, ra, s));
+            // R = I - sum of A_s X_t over every slice pair but A3 X3
+            static const int terms[8][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}, {0, 2}, {2, 0}, {1, 2}, {2, 1}};
+            for (int j = 0; j < kAccIters; ++j) {
+                GJ_TRY(launch_slice_global(X, ldx, n, ctl, Xs, kAccBeta, s));
+                for (int q = 0; q < 8; ++q) {
+                    GemmArgs a;
+                    std::memset(&a, 0, sizeof(a));
+                    a.M = a.N = a.K = n;
+                    a.A = As + terms[q][0] * nn; a.lda = n;
+                    a.B = Xs + terms[q][1] * nn; a.ldb = n;
+                    a.D = R; a.ldd = n;
+                    a.alpha = -1.0;
+                    if (q == 0) {
+                        a.gamma = 1.0;
+                    } else {
+                        a.C = R; a.ldc = n; a.beta = 1.0;
+                    }
+                    if (q == 7) a.norm_partials = pr;
+                    a.run_flag = ra;
+                    GJ_TRY(launch_gemm_f64(a, s));
+                }
+                GJ_TRY(launch_acc_check(ctl, j, s));
+                GemmArgs u;
+                std::memset(&u, 0, sizeof(u));
+                u.M = u.N = u.K = n;
+                u.A = X; u.lda = ldx; u.B = R; u.ldb = n; u.C = X; u.ldc = ldx; u.D = Xw; u.ldd = n;
+                u.alpha = 1.0; u.beta = 1.0;
+                u.run_flag = ra;
+                GJ_TRY(launch_gemm_f64(u, s));
+                GJ_TRY(launch_acc_copy(Xw, n, X, ldx, ctl, s));
+            }
+            GJ_TRY(launch_acc_finish(ctl, s));
+        }
     } else {
         GJ_TRY(launch_refine_finish(ctl, 1, __builtin_inf(), 1, s));
     }
@@ -1120,7 +1176,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     return GJ_OK;
 }
 
-size_t refined_ws(int n) { return refined_layout(n).end; }
+size_t refined_ws(int n, bool acc) { return refined_layout(n, acc).end; }
 
 // Residual of a plain FP64 result (want_resid): needs n^2 + partial sums.
 size_t resid_ws(int n) {
@@ -1208,7 +1264,7 @@ size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
         return solve_ws(n_or_batch, n_host[0], o.rule);
     }
     if (op == GJ_OP_INVERT_BATCHED) {
-        if (n_or_batch < 1 || !n_host || o.rule != 0) return 0;
+        if (n_or_batch < 1 || !n_host || o.rule != 0 || (o.flags & GJ_FLAG_ACCURATE)) return 0;
         if (o.precision == GJ_PREC_FP32_REFINED) {
             RefBatchPlan R;
             if (!plan_refined_batch(n_or_batch, n_host, R)) return 0;
@@ -1316,6 +1372,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
             !res)
             return GJ_E_INVALID_ARG;
         if (o.rule != 0) return GJ_E_UNSUPPORTED;   // the batch kernels search the full block
+        if (o.flags & GJ_FLAG_ACCURATE) return GJ_E_UNSUPPORTED;   // single matrices only
         if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
         for (int b = 0; b < batch; ++b)
             if (n_host[b] < 1 || n_host[b] > kMaxN || off_host[b] < 0 || piv_off_host[b] < 0)

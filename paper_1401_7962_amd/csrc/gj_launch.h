@@ -79,6 +79,10 @@ struct RefineCtl {
     double r0;             // ||R_0||_F
     double *partials;
     gj_result *res;
+    int32_t run_acc;       // accurate-residual phase still running
+    int32_t acc_updates;   // updates kept in that phase
+    double r_acc;          // ||R||_F of the last accurate residual
+    unsigned long long xmax_bits;   // max |X| of the current iterate, as bits (non-negative)
 };
 
 // Per-matrix buffers of the refined path (device pointers).
@@ -119,6 +123,17 @@ hipError_t launch_gather_perm(const RefMember *mem, const RefMember &single, voi
 hipError_t launch_det_combine(const RefMember *mem, const RefMember &single, void *ctls, int count,
                               hipStream_t s);
 hipError_t launch_refine_iters(void *ctls, int count, hipStream_t s);
+// accurate-residual phase (single matrix): see accurate.hip
+const int32_t *ctl_run_acc(const void *c);
+hipError_t launch_acc_prepare(void *ctl, int enabled, hipStream_t s);
+hipError_t launch_slice_rows(const double *A, int64_t lda, int n, double *S, int beta,
+                             const int32_t *run, hipStream_t s);
+hipError_t launch_slice_global(const double *X, int64_t ldx, int n, void *ctl, double *S, int beta,
+                               hipStream_t s);
+hipError_t launch_acc_check(void *ctl, int j, hipStream_t s);
+hipError_t launch_acc_copy(const double *src, int n, double *X, int64_t ldx, const void *ctl,
+                           hipStream_t s);
+hipError_t launch_acc_finish(void *ctl, hipStream_t s);
 int sumsq_blocks(int n);
 hipError_t launch_sumsq(const double *M, int64_t ld, int n, double *partials, hipStream_t s);
 hipError_t launch_resid(const double *pr, int nr, const double *pa, int na, const double *px, int nx,

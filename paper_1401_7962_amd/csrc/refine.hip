@@ -60,6 +60,10 @@ __global__ void refine_start_kernel(RefineCtl *ctls, int count) {
     ctl->always = 1;
     ctl->r = __builtin_inf();
     ctl->r0 = __builtin_inf();
+    ctl->run_acc = 0;
+    ctl->acc_updates = 0;
+    ctl->r_acc = __builtin_inf();
+    ctl->xmax_bits = 0ull;
 }
 
 __global__ void __launch_bounds__(256)

@@ -92,6 +92,13 @@ def test_workspace_size(lib):
     assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 9], part) == 0
     p32 = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_PIVOT_PARTIAL)
     assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None, p32) == 0
+    # accurate residuals: refined single matrices only; six more n^2 buffers
+    acc = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_ACCURATE)
+    ref = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED)
+    assert (gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None, acc)
+            >= gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None, ref) + 6 * 500 * 500 * 8)
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None, gj.make_opts(flags=gj.GJ_FLAG_ACCURATE)) == 0
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 9], acc) == 0
 
 
 def test_argument_checks_without_gpu(lib):
@@ -101,7 +108,7 @@ def test_argument_checks_without_gpu(lib):
     assert lib.gj_invert(0, fake, 1, fake, 1, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
     assert lib.gj_invert(4, fake, 3, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
     assert lib.gj_invert(4, None, 4, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
-    o = gj.make_opts(flags=8)
+    o = gj.make_opts(flags=16)
     assert lib.gj_invert(4, fake, 4, P(1 << 24), 4, fake, fake, fake, ctypes.byref(o), None, 0,
                          None) == gj.GJ_E_INVALID_ARG
     # X overlapping A

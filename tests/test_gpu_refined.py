@@ -93,6 +93,47 @@ def test_refined_counted_units(gj, stat, monkeypatch):
     assert _rel(X, Xo) <= 1e-12
 
 
+def _exact_pair(n, span, seed):
+    """A = H D H^T with H Sylvester-Hadamard (entries +-1) and D a diagonal of
+    powers of two spanning 2^span (cond(A) = 2^span): every entry of A and of
+    A^-1 = H D^-1 H^T / n^2 is an exact sum of powers of two, so both are
+    exact in FP64 and the forward error of a computed inverse is known."""
+    H = inputs.sylvester_hadamard(n)
+    rng = inputs.rng_for(0, seed)
+    e = rng.integers(0, span + 1, size=n)
+    e[0], e[1] = 0, span
+    A = (H * np.ldexp(1.0, e)) @ H.T
+    Ainv = (H * np.ldexp(1.0, -e)) @ H.T / float(n * n)
+    return A, Ainv
+
+
+@pytest.mark.parametrize("n,span", [(64, 20), (256, 20), (256, 24), (512, 16)])
+def test_accurate_residual_phase(gj, n, span):
+    """GJ_FLAG_ACCURATE: the FP64-residual loop leaves a forward error of
+    about n u cond(A); the updates with error-free split residuals bring it to
+    a few u, against an exactly known inverse."""
+    A, Ainv = _exact_pair(n, span, 6200 + n + span)
+    Xr, _, _, rr = _refined(gj, A)
+    Xa, _, _, ra = _refined(gj, A, flags=gj.GJ_FLAG_ACCURATE)
+    assert rr["code"] == 0 and ra["code"] == 0, (rr, ra)
+    err_r = _rel(Xr, Ainv)
+    err_a = _rel(Xa, Ainv)
+    assert err_a <= 8 * 2.0 ** -53, (err_a, err_r)
+    assert ra["refine_iters"] > rr["refine_iters"]
+    if span >= 20:
+        assert err_r >= 100 * err_a, (err_a, err_r)
+
+
+def test_accurate_phase_skipped_on_fallback(gj):
+    """When the FP32 elimination fails the plain FP64 result stands, with or
+    without the accurate phase."""
+    A = inputs.rng_for(0, 6300).standard_normal((40, 40)) * 1e-50
+    Xr, _, _, rr = _refined(gj, A)
+    Xa, _, _, ra = _refined(gj, A, flags=gj.GJ_FLAG_ACCURATE)
+    assert rr["code"] == ra["code"]
+    assert Xr.tobytes() == Xa.tobytes()
+
+
 @pytest.mark.parametrize("n", [64, 300])
 def test_refined_det_only(gj, n):
     A = inputs.conditioned(n, 1e3, inputs.rng_for(0, 6100 + n))
