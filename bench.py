@@ -205,10 +205,8 @@ def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
         lu_ref[idx] = torch.linalg.slogdet(M)[1].cpu().numpy()
         del M, base
     Xs = {}
-    for name, prec, flags in (("plain_fp64", gj.GJ_PREC_FP64, 0),
-                              ("fp32_refined", gj.GJ_PREC_FP32_REFINED, 0),
-                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE)):
-        opts = gj.make_opts(precision=prec, flags=flags)
+    for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
+        opts = gj.make_opts(precision=prec)
         X = torch.empty_like(A)
         ip = torch.empty(int(sizes.sum()), dtype=torch.int32, device="cuda")
         jp = torch.empty_like(ip)
