@@ -185,6 +185,32 @@ def test_det_matches_invert(gj, n):
     assert r["det_sign"] == ro["det_sign"]
 
 
+def test_batched_counted_units(gj, monkeypatch):
+    """A batch whose streaming members all use their full register chunks
+    (n = 900, 1000, 1000) runs one step launch with the work-unit counter:
+    each member has its own counters; small members go on chip.  Every member
+    must match the oracle bit for bit."""
+    import torch
+    monkeypatch.setenv("GJ_BIG_STATIC", "1")
+    monkeypatch.setenv("GJ_BIG_ROWS", "32")
+    sizes = np.array([1000, 64, 900, 1000, 5], dtype=np.int32)
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes.astype(np.int64) ** 2)[:-1]
+    rng = inputs.rng_for(0, 3300)
+    mats = [rng.standard_normal((int(n), int(n))) for n in sizes]
+    packed = np.concatenate([m.ravel() for m in mats])
+    A = torch.from_numpy(packed).to("cuda")
+    X, ipiv, jpiv, res, poff = gj.gj_invert_batched(sizes, offs, A)
+    torch.cuda.synchronize()
+    Xh, ih, jh = X.cpu().numpy(), ipiv.cpu().numpy(), jpiv.cpu().numpy()
+    rs = gj.results_to_dicts(res)
+    for b, M in enumerate(mats):
+        n = int(sizes[b])
+        got = (Xh[offs[b]:offs[b] + n * n].reshape(n, n), ih[poff[b]:poff[b] + n],
+               jh[poff[b]:poff[b] + n], rs[b])
+        _assert_same(M, got, oracle.gj_invert_f64(M), f"member {b} n={n}")
+
+
 def test_batched_mixed(gj):
     """A packed batch spanning the wavefront, workgroup and streaming paths,
     with planted rank-(n-1) members."""
