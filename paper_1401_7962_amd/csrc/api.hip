@@ -66,14 +66,15 @@ namespace {
 
 // ------------------------------------------------------------ tuning table
 // Written by the project's autotuner (paper_1401_7962_amd/tune.py) as lines
-//     big_rows <f32|f64> <n_min> <n_max> <rows per workgroup> [<counted %>]
+//     big_rows <f32|f64> <n_min> <n_max> <rows per workgroup> [<counted %> [<chunks>]]
 // and read once from $GJ_TUNE_FILE, else from gj_tune.txt beside libgj.so.
-// The optional last field is the share of a step's work units handed out by
-// the step kernel's counter (default 0: every unit taken by index).
-// $GJ_BIG_ROWS and $GJ_BIG_COUNTED, when set, override the two fields (the
-// autotuner uses them to sweep); $GJ_BIG_STATIC sets the units taken by
-// index per workgroup directly.
-struct TuneEntry { int fp32, nmin, nmax, rows, counted; };
+// The optional fields are the share of a step's work units handed out by
+// the step kernel's counter (default 0: every unit taken by index) and the
+// register chunks a thread aims to fill (default 8; fewer means more threads
+// per row).  $GJ_BIG_ROWS, $GJ_BIG_COUNTED and $GJ_BIG_CHUNKS, when set,
+// override the three fields (the autotuner uses them to sweep);
+// $GJ_BIG_STATIC sets the units taken by index per workgroup directly.
+struct TuneEntry { int fp32, nmin, nmax, rows, counted, chunks; };
 std::vector<TuneEntry> g_tune;
 std::once_flag g_tune_once;
 
@@ -94,11 +95,12 @@ void load_tune_table() {
     char line[256];
     while (std::fgets(line, sizeof(line), fp)) {
         char key[64], prec[16];
-        int lo, hi, v, pct = 0;
-        const int got = std::sscanf(line, "%63s %15s %d %d %d %d", key, prec, &lo, &hi, &v, &pct);
+        int lo, hi, v, pct = 0, ch = 8;
+        const int got = std::sscanf(line, "%63s %15s %d %d %d %d %d", key, prec, &lo, &hi, &v, &pct, &ch);
         if (got >= 5 && std::strcmp(key, "big_rows") == 0 && v >= 1 && v <= 64 && lo <= hi) {
             if (got < 6 || pct < 0 || pct > 90) pct = 0;
-            g_tune.push_back(TuneEntry{std::strcmp(prec, "f32") == 0 ? 1 : 0, lo, hi, v, pct});
+            if (got < 7 || ch < 1 || ch > 8) ch = 8;
+            g_tune.push_back(TuneEntry{std::strcmp(prec, "f32") == 0 ? 1 : 0, lo, hi, v, pct, ch});
         }
     }
     std::fclose(fp);
@@ -137,15 +139,18 @@ BigShape big_shape(int n, bool fp32, int nt, int ncol = 0) {
     s.ncol = ncol;
     s.rhs0 = n;
     s.nt = nt;
-    // threads per row: just enough for 8 vector chunks per thread, so that
-    // every thread's registers are used (a wavefront may span several rows)
-    int need = (ncol + 8 * ve - 1) / (8 * ve);
+    // threads per row: just enough for the tuned number of vector chunks per
+    // thread (8 by default, so that every thread's registers are used; a
+    // wavefront may span several rows)
+    const TuneEntry *te = tuned(fp32, n);
+    int chunks = env_int("GJ_BIG_CHUNKS", 0);
+    if (chunks < 1 || chunks > 8) chunks = te ? te->chunks : 8;
+    int need = (ncol + chunks * ve - 1) / (chunks * ve);
     int tpr = 4;
     while (tpr < need) tpr <<= 1;
     if (tpr > nt) tpr = nt;
     s.tpr = tpr;
     const int rg = nt / tpr;
-    const TuneEntry *te = tuned(fp32, n);
     int R = env_int("GJ_BIG_ROWS", 0);
     if (R <= 0 && te) R = te->rows;
     if (R <= 0) R = std::max(1, n / 512);

@@ -7,11 +7,13 @@ less memory-level parallelism.  This script times every admissible R for
 each size bucket and precision on the GPU it runs on, then, with the best
 R, the share of a step's work units left to the step kernel's counter (the
 rest are taken by workgroup index; units from the counter let faster parts
-of the chip sweep more rows, at the cost of a barrier per unit).  The
-winners go to gj_tune.txt beside libgj.so, which the library reads at its
-first call:
+of the chip sweep more rows, at the cost of a barrier per unit) and, where
+no units go to the counter, fewer register chunks per thread (more threads
+per row, so more loads in flight per row at the cost of more workgroup-wide
+reductions).  The winners go to gj_tune.txt beside libgj.so, which the
+library reads at its first call:
 
-    big_rows <f32|f64> <n_min> <n_max> <R> <counted %>
+    big_rows <f32|f64> <n_min> <n_max> <R> <counted %> <chunks>
 
 Buckets up to n = 1024 are timed as packed batches (about 128 MiB of
 matrices, the batched use case); larger ones as single inversions.  FP64 is
@@ -34,6 +36,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 BUCKETS = [(129, 256), (257, 512), (513, 1024), (1025, 2048), (2049, 4096), (4097, 8192)]
 CANDIDATES = [1, 2, 4, 8, 16, 32, 64]
 COUNTED = [25, 37, 50]   # percent of a step's units from the counter (0: none)
+CHUNKS = [4]             # register chunks per thread tried besides the default 8
 
 
 def _time(fn, reps):
@@ -128,19 +131,31 @@ def main(argv=None):
                 ctimes[pct] = _time(run, 1 if args.quick or n >= 4096 else 2)
                 print(f"tune {'f32' if fp32 else 'f64'} n={n} R={best} counted={pct}%: "
                       f"{ctimes[pct]:.2f} ms", flush=True)
-            os.environ.pop("GJ_BIG_ROWS", None)
             os.environ.pop("GJ_BIG_COUNTED", None)
             pct = min(ctimes, key=ctimes.get)
             if ctimes[pct] > 0.99 * ctimes[0]:   # keep the barrier-free sweep unless it clearly loses
                 pct = 0
-            lines.append(f"big_rows {'f32' if fp32 else 'f64'} {lo} {hi} {best} {pct}")
+            chtimes = {8: times[best]}
+            if pct == 0 and n > 1024:   # the counter needs all 8 chunks
+                for ch in CHUNKS:
+                    os.environ["GJ_BIG_CHUNKS"] = str(ch)
+                    chtimes[ch] = _time(run, 1 if args.quick or n >= 4096 else 2)
+                    print(f"tune {'f32' if fp32 else 'f64'} n={n} R={best} chunks={ch}: "
+                          f"{chtimes[ch]:.2f} ms", flush=True)
+                os.environ.pop("GJ_BIG_CHUNKS", None)
+            os.environ.pop("GJ_BIG_ROWS", None)
+            ch = min(chtimes, key=chtimes.get)
+            if chtimes[ch] > 0.99 * chtimes[8]:
+                ch = 8
+            lines.append(f"big_rows {'f32' if fp32 else 'f64'} {lo} {hi} {best} {pct} {ch}")
             report.append({"prec": "f32" if fp32 else "f64", "bucket": [lo, hi], "n": n,
-                           "ms": times, "best": best, "counted_ms": ctimes, "counted": pct})
+                           "ms": times, "best": best, "counted_ms": ctimes, "counted": pct,
+                           "chunks_ms": chtimes, "chunks": ch})
             del run
             torch.cuda.empty_cache()
     with open(args.out, "w") as f:
         f.write("# streaming elimination: rows per workgroup, chosen by paper_1401_7962_amd/tune.py\n")
-        f.write("# big_rows <precision> <n_min> <n_max> <rows> <counted %>\n")
+        f.write("# big_rows <precision> <n_min> <n_max> <rows> <counted %> [<chunks per thread>]\n")
         f.write("\n".join(lines) + "\n")
     print(json.dumps(report), flush=True)
 
