@@ -130,6 +130,16 @@ def test_streaming_work_units(gj, n, rows, stat, monkeypatch):
     assert r["det_sign"] == want[3]["det_sign"]
 
 
+@pytest.mark.parametrize("n,chunks", [(1100, 4), (1100, 2), (2100, 4), (1500, 1)])
+def test_streaming_chunks_per_thread(gj, n, chunks, monkeypatch):
+    """Wider rows than the default shape (fewer register chunks per thread,
+    more threads per row; 1 chunk clamps the row to the workgroup): the
+    inverse and the pivots must still match the oracle bit for bit."""
+    monkeypatch.setenv("GJ_BIG_CHUNKS", str(chunks))
+    A = inputs.rng_for(0, 3300 + n + chunks).standard_normal((n, n))
+    _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n} chunks={chunks}")
+
+
 @pytest.mark.parametrize("n", [4, 16, 64, 128, 256, 512])
 def test_hadamard_ties(gj, n):
     """Every candidate ties at every step: the tie-break on the swapped
