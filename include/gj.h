@@ -92,7 +92,7 @@ enum {
                                  singular.  Not both; not with GJ_PREC_FP32_REFINED or
                                  gj_invert_batched (GJ_E_UNSUPPORTED).  Every order then goes
                                  through the streaming kernels. */
-    GJ_FLAG_ACCURATE = 8      /* GJ_PREC_FP32_REFINED only (else GJ_E_INVALID_ARG), gj_invert
+    GJ_FLAG_ACCURATE = 8,     /* GJ_PREC_FP32_REFINED only (else GJ_E_INVALID_ARG), gj_invert
                                  (gj_invert_batched: GJ_E_UNSUPPORTED): after the FP64
                                  Newton-Schulz loop, up to 2 more updates with residuals
                                  I - A X formed from error-free split products on the FP64
@@ -100,6 +100,19 @@ enum {
                                  residual stalls at about n u cond(A); these bring the forward
                                  error of X to about u.  gj_result.refine_iters counts all
                                  updates kept.  The workspace grows by 6 n^2 doubles. */
+    GJ_FLAG_BLOCKED = 16      /* gj_invert, GJ_PREC_FP64 with the full search only (else
+                                 GJ_E_INVALID_ARG; gj_det, gj_solve, gj_invert_batched:
+                                 GJ_E_UNSUPPORTED): delayed updates.  Each step eliminates on the
+                                 trailing block of rows and columns not yet pivoted (all that the
+                                 full search of Obs. 2-3 reads); every 128 steps the other rows
+                                 and columns receive those steps' eqs. 14-15 at once as FP64
+                                 matrix-core products (the theorem of section 1: the left
+                                 factors of the elimination may be grouped).  Pivots, rank,
+                                 result code and determinant are bit-identical to the unblocked
+                                 elimination; the inverse agrees up to rounding (the products
+                                 sum in another order), not bit for bit.  Orders up to 128 run
+                                 the on-chip kernel as without the flag.  The workspace holds two
+                                 n x (n + padding) arrays.  step_events are not recorded. */
 };
 
 /* gj_workspace_size op codes */

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgj.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "onchip.hip", "big.hip", "gemm.hip", "refine.hip", "accurate.hip"]
+SOURCES = ["api.hip", "onchip.hip", "big.hip", "gemm.hip", "refine.hip", "accurate.hip", "blocked.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

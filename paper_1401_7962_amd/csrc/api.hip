@@ -39,9 +39,13 @@ bool read_opts(const gj_opts *o, Opts &out) {
     if (o->precision != GJ_PREC_FP64 && o->precision != GJ_PREC_FP32_REFINED) return false;
     if (o->want_resid != 0 && o->want_resid != 1) return false;
     if (o->max_refine_iters < 0 || o->max_refine_iters > 100) return false;
-    if (o->flags & ~(GJ_FLAG_REUSE_PLAN | GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM | GJ_FLAG_ACCURATE))
+    if (o->flags & ~(GJ_FLAG_REUSE_PLAN | GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM | GJ_FLAG_ACCURATE |
+                     GJ_FLAG_BLOCKED))
         return false;
     if ((o->flags & GJ_FLAG_ACCURATE) && o->precision != GJ_PREC_FP32_REFINED) return false;
+    if ((o->flags & GJ_FLAG_BLOCKED) &&
+        (o->precision != GJ_PREC_FP64 || (o->flags & (GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM))))
+        return false;
     if ((o->flags & GJ_FLAG_PIVOT_PARTIAL) && (o->flags & GJ_FLAG_PIVOT_PROGRAM)) return false;
     if (std::isnan(o->zero_tol)) return false;
     out.precision = o->precision;
@@ -366,11 +370,142 @@ size_t resid_ws(int n);
 struct RefinedLayout;
 size_t refined_ws(int n, bool acc);
 
+// ------------------------------------------------ blocked elimination
+// Panels of kBlkNb steps on the trailing block, then the delayed updates as
+// FP64 matrix-core products (blocked.hip).  The array's row stride covers
+// every panel's row shape from its block's first column (a block of order m
+// at column k0 sweeps k0 + ldw(m) columns); two arrays alternate, one
+// panel's pivot-ordered copy being the next one's input.
+constexpr int kBlkNb = 128;
+
+struct BlkLayout {
+    BigBufs bb;      // streaming buffers (W: the first array), sized for the largest panel
+    int64_t ldw;
+    int nb, nblk;    // panel width; most workgroups of any panel's step
+    size_t W2, tA, tB, perm, end;
+};
+
+BlkLayout blk_layout(int n) {
+    BlkLayout L;
+    int nb = env_int("GJ_BLK_NB", kBlkNb);   // panel width (experiments)
+    L.nb = std::max(2, std::min(nb, 1024)) & ~1;   // even: block starts stay 16-byte aligned
+    int64_t ldw = n;
+    int nblk = 1;
+    for (int k0 = 0; k0 < n; k0 += L.nb) {
+        const int m = n - k0;
+        const BigShape s = big_shape(m, false, big_threads(m, false));
+        ldw = std::max<int64_t>(ldw, k0 + s.ldw);
+        nblk = std::max(nblk, s.nblk);
+    }
+    L.ldw = (ldw + 15) / 16 * 16;
+    L.nblk = nblk;
+    BigShape s0 = big_shape(n, false, big_threads(n, false));
+    s0.ldw = L.ldw;
+    s0.nblk = nblk;
+    L.bb = big_bufs(s0, false, 0);
+    size_t c = L.bb.end;
+    L.W2 = c; c = a256(c + (size_t)n * L.ldw * 8);
+    L.tA = c; c = a256(c + (size_t)n * L.nb * 8);     // k0 x nb, ld nb
+    L.tB = c; c = a256(c + (size_t)n * L.nb * 8);     // nb x k0, ld n
+    L.perm = c; c = a256(c + (size_t)6 * n * 4);      // prow[2], pcol[2], rowinv, colinv
+    L.end = c;
+    return L;
+}
+
+gj_status run_blocked(int n, const double *A, int64_t lda, double *X, int64_t ldx, int32_t *ipiv,
+                      int32_t *jpiv, gj_result *res, const Opts &o, void *ws, size_t ws_bytes,
+                      hipStream_t s) {
+    const BlkLayout L = blk_layout(n);
+    if (ws_bytes < L.end) return GJ_E_WORKSPACE;
+    char *w = (char *)ws;
+    const int64_t ldw = L.ldw;
+    double *Wb[2] = {reinterpret_cast<double *>(w + L.bb.W), reinterpret_cast<double *>(w + L.W2)};
+    double *tA = reinterpret_cast<double *>(w + L.tA), *tB = reinterpret_cast<double *>(w + L.tB);
+    int32_t *perm = reinterpret_cast<int32_t *>(w + L.perm);
+    int32_t *prow[2] = {perm, perm + n}, *pcol[2] = {perm + 2 * n, perm + 3 * n};
+    int32_t *rowinv = perm + 4 * n, *colinv = perm + 5 * n;
+    StepRec *steps = reinterpret_cast<StepRec *>(w + L.bb.steps);
+    BigHdr *hdr = reinterpret_cast<BigHdr *>(w + L.bb.hdr);
+    hipError_t e = launch_blk_init_perm(prow[0], pcol[0], n, s);
+    if (e != hipSuccess) return hip_fail(e);
+    int cur = 0;
+    for (int k0 = 0; k0 < n; k0 += L.nb) {
+        const int m = n - k0, nbp = std::min(L.nb, m);
+        const int nt = big_threads(m, false);
+        const BigShape sh = big_shape(m, false, nt);
+        // the block's row shape and candidate list fit the layout
+        if (k0 + sh.ldw > ldw || sh.nblk > L.nblk) return GJ_E_WORKSPACE;
+        BigDesc d = make_desc(sh, L.bb, w, A, lda, X, ldx, ipiv, jpiv, res);
+        d.W = Wb[cur] + (int64_t)k0 * ldw + k0;
+        d.ldw = ldw;
+        d.mstride = ldw;
+        d.steps = steps + k0;
+        d.k0 = k0;
+        d.inplace = k0 > 0;
+        // nbp steps on the trailing block, no finish
+        e = launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false),
+                       big_counted(sh), false, 0, nullptr, nullptr, d, nullptr, sh.nblk, 0, nbp, 0,
+                       o.zero_tol, kEps64, 0, nullptr, nullptr, s);
+        if (e != hipSuccess) return hip_fail(e);
+        e = launch_blk_panel_end(hdr, d.rowlog + (size_t)(nbp & 1) * ldw,
+                                 d.collog + (size_t)(nbp & 1) * ldw, m, d.rowphys, d.colphys,
+                                 steps + k0, nbp, k0, Wb[cur], Wb[cur ^ 1], ldw, n, tA, L.nb, tB,
+                                 n, prow[cur], pcol[cur], prow[cur ^ 1], pcol[cur ^ 1], s);
+        if (e != hipSuccess) return hip_fail(e);
+        cur ^= 1;
+        if (k0 == 0) continue;
+        // the panel's steps on the other rows and columns (b: the panel's
+        // pivots, 1: the k0 earlier ones, 3: the rest)
+        double *Wc = Wb[cur];
+        GemmArgs g;
+        std::memset(&g, 0, sizeof(g));
+        g.alpha = 1.0;
+        // W_b1 = T W_b1(old)
+        g.M = nbp; g.N = k0; g.K = nbp;
+        g.A = Wc + (int64_t)k0 * ldw + k0; g.lda = ldw;
+        g.B = tB; g.ldb = n;
+        g.D = Wc + (int64_t)k0 * ldw; g.ldd = ldw;
+        e = launch_gemm_f64(g, s);
+        if (e != hipSuccess) return hip_fail(e);
+        // W_31 += W_3b W_b1(old), W_3b = -W_3b(old) T from the panel
+        if (m > nbp) {
+            g.M = m - nbp; g.N = k0; g.K = nbp;
+            g.A = Wc + (int64_t)(k0 + nbp) * ldw + k0; g.lda = ldw;
+            g.B = tB; g.ldb = n;
+            g.C = Wc + (int64_t)(k0 + nbp) * ldw; g.ldc = ldw;
+            g.D = Wc + (int64_t)(k0 + nbp) * ldw; g.ldd = ldw;
+            g.beta = 1.0;
+            e = launch_gemm_f64(g, s);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        // W_1* -= W_1b(old) W_b* (W_1b zeroed by the copy: it becomes -W_1b(old) T)
+        g.M = k0; g.N = n; g.K = nbp;
+        g.A = tA; g.lda = L.nb;
+        g.B = Wc + (int64_t)k0 * ldw; g.ldb = ldw;
+        g.C = Wc; g.ldc = ldw;
+        g.D = Wc; g.ldd = ldw;
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        e = launch_gemm_f64(g, s);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    e = launch_blk_finish(hdr, steps, n, ipiv, jpiv, res, prow[cur], pcol[cur], rowinv, colinv,
+                          Wb[cur], ldw, X, ldx, s);
+    if (e != hipSuccess) return hip_fail(e);
+    return GJ_OK;
+}
+
+bool use_blocked(int n, const Opts &o, bool det_only) {
+    return (o.flags & GJ_FLAG_BLOCKED) && !det_only && n > kOnchipMax;
+}
+
 size_t single_ws(int n, const Opts &o, bool det_only) {
     if (o.precision == GJ_PREC_FP32_REFINED)
         return refined_ws(n, (o.flags & GJ_FLAG_ACCURATE) && !det_only);
     size_t need = 256;
-    if (n > kOnchipMax || o.rule != 0) {
+    if (use_blocked(n, o, det_only)) {
+        need = blk_layout(n).end;
+    } else if (n > kOnchipMax || o.rule != 0) {
         BigShape s = big_shape(n, false, big_threads(n, false));
         need = big_bufs(s, false, 0).end;
     }
@@ -1261,15 +1396,17 @@ size_t gj_workspace_size(int32_t op, int32_t n_or_batch, const int32_t *n_host,
     if (op == GJ_OP_INVERT || op == GJ_OP_DET) {
         if (n_or_batch < 1 || n_or_batch > kMaxN) return 0;
         if (o.rule != 0 && o.precision != GJ_PREC_FP64) return 0;
+        if (op == GJ_OP_DET && (o.flags & GJ_FLAG_BLOCKED)) return 0;
         return single_ws(n_or_batch, o, op == GJ_OP_DET);
     }
     if (op == GJ_OP_SOLVE) {
         if (n_or_batch < 1 || !n_host || n_host[0] < 1 || n_or_batch + n_host[0] > kMaxN) return 0;
-        if (o.precision != GJ_PREC_FP64 || o.want_resid) return 0;
+        if (o.precision != GJ_PREC_FP64 || o.want_resid || (o.flags & GJ_FLAG_BLOCKED)) return 0;
         return solve_ws(n_or_batch, n_host[0], o.rule);
     }
     if (op == GJ_OP_INVERT_BATCHED) {
-        if (n_or_batch < 1 || !n_host || o.rule != 0 || (o.flags & GJ_FLAG_ACCURATE)) return 0;
+        if (n_or_batch < 1 || !n_host || o.rule != 0 || (o.flags & (GJ_FLAG_ACCURATE | GJ_FLAG_BLOCKED)))
+            return 0;
         if (o.precision == GJ_PREC_FP32_REFINED) {
             RefBatchPlan R;
             if (!plan_refined_batch(n_or_batch, n_host, R)) return 0;
@@ -1308,10 +1445,14 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
         hipStream_t s = (hipStream_t)stream;
         if (o.precision == GJ_PREC_FP32_REFINED)
             return run_refined_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, (char *)ws, s, false);
-        gj_status st = run_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes, s, false);
+        const bool blocked = use_blocked(n, o, false);
+        gj_status st = blocked ? run_blocked(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes, s)
+                               : run_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes, s, false);
         if (st != GJ_OK || !o.want_resid) return st;
         size_t off = 0;
-        if (n > kOnchipMax || o.rule != 0)
+        if (blocked)
+            off = a256(blk_layout(n).end);
+        else if (n > kOnchipMax || o.rule != 0)
             off = a256(big_bufs(big_shape(n, false, big_threads(n, false)), false, 0).end);
         return run_resid(n, A, lda, X, ldx, res, (char *)ws + off, s);
     } catch (...) {
@@ -1326,6 +1467,7 @@ gj_status gj_det(int32_t n, const double *A, int64_t lda, int32_t *ipiv, int32_t
         if (!read_opts(opts, o)) return GJ_E_INVALID_ARG;
         if (n < 1 || lda < n || !A || !ipiv || !jpiv || !res) return GJ_E_INVALID_ARG;
         if (n > kMaxN || (o.rule != 0 && o.precision != GJ_PREC_FP64)) return GJ_E_UNSUPPORTED;
+        if (o.flags & GJ_FLAG_BLOCKED) return GJ_E_UNSUPPORTED;
         const size_t need = single_ws(n, o, true);
         if (needs_ws(n, o, true)) {
             if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
@@ -1349,7 +1491,8 @@ gj_status gj_solve(int32_t n, int32_t m, const double *A, int64_t lda, const dou
         if (n < 1 || m < 1 || lda < n || ldb < m || ldx < m || !A || !B || !X || !ipiv || !jpiv ||
             !res)
             return GJ_E_INVALID_ARG;
-        if ((int64_t)n + m > kMaxN || o.precision != GJ_PREC_FP64 || o.want_resid)
+        if ((int64_t)n + m > kMaxN || o.precision != GJ_PREC_FP64 || o.want_resid ||
+            (o.flags & GJ_FLAG_BLOCKED))
             return GJ_E_UNSUPPORTED;
         const size_t abytes = ((size_t)(n - 1) * lda + n) * 8;
         const size_t bbytes = ((size_t)(n - 1) * ldb + m) * 8, xbytes = ((size_t)(n - 1) * ldx + m) * 8;
@@ -1377,7 +1520,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
             !res)
             return GJ_E_INVALID_ARG;
         if (o.rule != 0) return GJ_E_UNSUPPORTED;   // the batch kernels search the full block
-        if (o.flags & GJ_FLAG_ACCURATE) return GJ_E_UNSUPPORTED;   // single matrices only
+        if (o.flags & (GJ_FLAG_ACCURATE | GJ_FLAG_BLOCKED)) return GJ_E_UNSUPPORTED;   // single matrices only
         if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
         for (int b = 0; b < batch; ++b)
             if (n_host[b] < 1 || n_host[b] > kMaxN || off_host[b] < 0 || piv_off_host[b] < 0)

@@ -40,6 +40,11 @@
 //     rhs0: n, or the end of A's last register chunk), get the same eq. 14-15
 //     updates and are never pivot candidates.  The column swaps of A come
 //     back as row swaps of the result: X(i, j) = W(rowphys[collog[i]], rhs0 + j).
+//   * The blocked elimination (blocked.hip) runs these kernels on the
+//     trailing block of a larger array for a few steps at a time: W then
+//     points into that array, d.k0 counts the steps already taken (the zero
+//     threshold and the rank are global) and d.inplace makes the init kernel
+//     read the block where it is and keep the header.
 #include <type_traits>
 
 #include "gj_device.h"
@@ -195,7 +200,7 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     T *W = reinterpret_cast<T *>(d.W);
     const int r0 = rb * d.R, r1 = min(n, r0 + d.R);
     if (rb == 0 && t == 0) {
-        d.hdr->status = 0; d.hdr->rank = n; d.hdr->tau = 0.0;
+        if (!d.inplace) { d.hdr->status = 0; d.hdr->rank = n; d.hdr->tau = 0.0; }
         d.hdr->ticket[0] = 0; d.hdr->ticket[1] = 0;
     }
     if (rb == 0)
@@ -206,11 +211,13 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     bool nf = false;
     for (int i = r0 + rsub; i < r1; i += rg) {
         if (tc == 0) d.rowlog[i] = i;
-        for (int j = tc; j < d.ldw; j += tpr) {
+        // in place: only the block's own columns (the row stride reaches
+        // past them into the rest of the array)
+        for (int j = tc; j < (d.inplace ? n : d.ldw); j += tpr) {
             T x = (T)0;
             if (j >= d.rhs0 && j < d.ncol) x = (T)d.B[(int64_t)i * d.ldb + (j - d.rhs0)];   // solve: D^0 = B
             if (j < n) {
-                x = (T)d.A[(int64_t)i * d.lda + j];
+                x = d.inplace ? W[(int64_t)i * d.ldw + j] : (T)d.A[(int64_t)i * d.lda + j];
                 const double ax = fabs((double)x);
                 // candidates: the whole matrix, or column 0 for the other
                 // rules; the program's rule scores the value itself and takes
@@ -222,7 +229,7 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 const uint32_t key = ((uint32_t)i << 16) | (uint32_t)j;
                 if (cand && better(sc, key, ba, bk)) { ba = sc; bv = (double)x; bk = key; bi = i; bj = j; }
             }
-            W[(int64_t)i * d.ldw + j] = x;
+            if (!d.inplace) W[(int64_t)i * d.ldw + j] = x;
         }
     }
     const int any_nf = __syncthreads_or(nf ? 1 : 0);
@@ -337,7 +344,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     }
     block_argmax<NT>(pa, pv, pk, pi, pj, s_a, s_v, s_k, s_i, s_j);
     double tau;
-    if (k == 0) {
+    if (k == 0 && d.k0 == 0) {
         // preset threshold: n eps max|a| for the text's rule, none (0) for the
         // others (the program has none)
         tau = (zero_tol >= 0.0) ? (double)(T)zero_tol
@@ -354,7 +361,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     if (stop_nf || stop_sing) {
         if (rb == 0 && t == 0) {
             hdr->status = stop_nf ? GJ_RES_NONFINITE : GJ_RES_SINGULAR;
-            hdr->rank = k;
+            hdr->rank = d.k0 + k;
         }
         return;
     }
@@ -793,6 +800,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         e = hipEventRecord((hipEvent_t)events[1], s);
         if (e != hipSuccess) return e;
     }
+    if (grid_finish == 0) return hipSuccess;   // steps only (a panel of the blocked elimination)
     hipLaunchKernelGGL((gj_big_finish<T>), dim3(grid_finish), dim3(256), 0, s, descs, bmap, single, run_flag);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -304,6 +304,8 @@ struct BigDesc {
     int32_t rule;             // pivot rule: 0 full (Obs. 2-3), 1 partial on |a|, 2 the program's (section 3)
     const double *B;          // solve: right-hand sides, n x m (ldb); X receives A^-1 B (n x m, ldx)
     int64_t ldb;
+    int32_t k0;               // blocked elimination: steps before this panel (0 otherwise)
+    int32_t inplace;          // init: W already holds the trailing block (no copy, header kept)
 };
 
 }  // namespace gj

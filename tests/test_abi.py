@@ -99,6 +99,16 @@ def test_workspace_size(lib):
             >= gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None, ref) + 6 * 500 * 500 * 8)
     assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None, gj.make_opts(flags=gj.GJ_FLAG_ACCURATE)) == 0
     assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 9], acc) == 0
+    # delayed updates: two padded n x n arrays; orders up to 128 stay on chip (no workspace)
+    blk = gj.make_opts(flags=gj.GJ_FLAG_BLOCKED)
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 4096, None, blk) >= 2 * 4096 * 4096 * 8
+    assert (gj.gj_workspace_size(gj.GJ_OP_INVERT, 64, None, blk)
+            == gj.gj_workspace_size(gj.GJ_OP_INVERT, 64, None, gj.make_opts()))
+    assert gj.gj_workspace_size(gj.GJ_OP_DET, 500, None, blk) == 0
+    assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 500, [2], blk) == 0
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 900], blk) == 0
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None,
+                                gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_BLOCKED)) == 0
 
 
 def test_argument_checks_without_gpu(lib):
@@ -108,9 +118,21 @@ def test_argument_checks_without_gpu(lib):
     assert lib.gj_invert(0, fake, 1, fake, 1, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
     assert lib.gj_invert(4, fake, 3, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
     assert lib.gj_invert(4, None, 4, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
-    o = gj.make_opts(flags=16)
+    o = gj.make_opts(flags=32)
     assert lib.gj_invert(4, fake, 4, P(1 << 24), 4, fake, fake, fake, ctypes.byref(o), None, 0,
                          None) == gj.GJ_E_INVALID_ARG
+    # delayed updates: FP64 full search only; not for the determinant, solve or batches
+    for bad in (gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_BLOCKED),
+                gj.make_opts(flags=gj.GJ_FLAG_BLOCKED | gj.GJ_FLAG_PIVOT_PARTIAL)):
+        assert lib.gj_invert(4, fake, 4, P(1 << 24), 4, fake, fake, fake, ctypes.byref(bad), None, 0,
+                             None) == gj.GJ_E_INVALID_ARG
+    blk = gj.make_opts(flags=gj.GJ_FLAG_BLOCKED)
+    assert lib.gj_det(300, P(1 << 30), 300, fake, fake, fake, ctypes.byref(blk), None, 0,
+                      None) == gj.GJ_E_UNSUPPORTED
+    assert lib.gj_solve(8, 2, P(1 << 30), 8, P(1 << 34), 2, P(1 << 38), 2, fake, fake, fake,
+                        ctypes.byref(blk), None, 0, None) == gj.GJ_E_UNSUPPORTED
+    assert lib.gj_invert(1000, P(1 << 30), 1000, P(1 << 40), 1000, fake, fake, fake, ctypes.byref(blk),
+                         None, 0, None) == gj.GJ_E_WORKSPACE
     # X overlapping A
     assert lib.gj_invert(4, fake, 4, fake, 4, fake, fake, fake, None, None, 0, None) == gj.GJ_E_INVALID_ARG
     # large n needs a workspace
