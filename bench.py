@@ -382,6 +382,61 @@ def bench_solve(n: int = 4096, m: int = 16, reps: int = 3):
             "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def bench_blocked(sizes=(4096, 8192), reps: int = 3):
+    """Delayed updates (GJ_FLAG_BLOCKED) against the unblocked elimination on
+    the same input (the headline's at 4096, a diagonally weighted uniform one
+    at 8192): time per inversion, the steps' algorithmic sweep bytes
+    sum_k 16 (n - k0(k))^2 over the whole-inversion time, identical pivots,
+    and the distance between the two inverses."""
+    import torch
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    out = {}
+    stream = torch.cuda.current_stream()
+    for n in sizes:
+        if n == 4096:
+            A = torch.from_numpy(inputs.single_dominant(n)).to("cuda")
+        else:
+            A = torch.from_numpy(inputs.rng_for(0, 8800 + n).uniform(-1.0, 1.0, (n, n))).to("cuda")
+            A.diagonal().add_(4.0)
+        row = {}
+        Xs, pivs = {}, {}
+        for name, flags in (("unblocked", 0), ("blocked", gj.GJ_FLAG_BLOCKED)):
+            o = gj.make_opts(flags=flags)
+            X = torch.empty_like(A)
+            ip = torch.empty(n, dtype=torch.int32, device="cuda")
+            jp = torch.empty_like(ip)
+            res = torch.empty(gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+            ws = torch.empty(gj.gj_workspace_size(gj.GJ_OP_INVERT, n, None, o), dtype=torch.uint8, device="cuda")
+            gj.gj_invert(A, X, ip, jp, res, o, ws)
+            torch.cuda.synchronize()
+            e = _events(2 * reps, stream)
+            for k in range(reps):
+                e[2 * k].record()
+                gj.gj_invert(A, X, ip, jp, res, o, ws)
+                e[2 * k + 1].record()
+            torch.cuda.synchronize()
+            ms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+            r = gj.results_to_dicts(res)[0]
+            row[name] = {"ms": round(ms, 2), "inv_per_s": round(1e3 / ms, 3), "code": r["code"]}
+            Xs[name], pivs[name] = X, (ip.clone(), jp.clone(), r["det_mant"], r["det_exp"], r["det_sign"])
+            del ws
+        nb = 256   # the library's panel width (steps per delayed update)
+        sweep = sum(16.0 * (n - (k // nb) * nb) ** 2 for k in range(n))
+        row["blocked"]["step_sweep_bytes"] = sweep
+        row["blocked"]["sweep_gbs_over_total_time"] = round(sweep / (row["blocked"]["ms"] * 1e-3) / 1e9, 1)
+        row["speedup_blocked_over_unblocked"] = round(row["unblocked"]["ms"] / row["blocked"]["ms"], 3)
+        pu, pb = pivs["unblocked"], pivs["blocked"]
+        row["same_pivots_and_det"] = bool(torch.equal(pu[0], pb[0]) and torch.equal(pu[1], pb[1])
+                                          and pu[2:] == pb[2:])
+        row["blocked_vs_unblocked_rel_frobenius"] = float(
+            torch.linalg.norm(Xs["blocked"] - Xs["unblocked"]) / torch.linalg.norm(Xs["unblocked"]))
+        out[str(n)] = row
+        del Xs, A
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_pivot_rules(n: int = 4096, n_growth: int = 512, reps: int = 2):
     """The three pivot rules on the GPU: time per inversion of the headline
     input, and the normwise residual ||A X - I||_F / (||A||_F ||X||_F) on a
@@ -492,7 +547,8 @@ LEGS = {"latency_small": lambda: bench_latency_small(),
         "batch_conditioned_20k": lambda: bench_batch_conditioned(),
         "solve_4096": lambda: bench_solve(),
         "pivot_rules": lambda: bench_pivot_rules(),
-        "accuracy_exact_4096": lambda: bench_accuracy_exact()}
+        "accuracy_exact_4096": lambda: bench_accuracy_exact(),
+        "blocked": lambda: bench_blocked()}
 
 
 def main():
@@ -586,6 +642,9 @@ def main():
         torch.cuda.empty_cache()
         extras["accuracy_exact_4096"] = bench_accuracy_exact()
         print("bench: exact-inverse accuracy done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["blocked"] = bench_blocked()
+        print("bench: blocked elimination done", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["extras"] = extras
     if not args.no_cpu_baseline:

@@ -104,7 +104,7 @@ enum {
                                  GJ_E_INVALID_ARG; gj_det, gj_solve, gj_invert_batched:
                                  GJ_E_UNSUPPORTED): delayed updates.  Each step eliminates on the
                                  trailing block of rows and columns not yet pivoted (all that the
-                                 full search of Obs. 2-3 reads); every 128 steps the other rows
+                                 full search of Obs. 2-3 reads); every 256 steps the other rows
                                  and columns receive those steps' eqs. 14-15 at once as FP64
                                  matrix-core products (the theorem of section 1: the left
                                  factors of the elimination may be grouped).  Pivots, rank,

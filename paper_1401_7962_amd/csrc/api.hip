@@ -135,7 +135,7 @@ int big_threads(int n, bool fp32) {
     return 1024;
 }
 
-BigShape big_shape(int n, bool fp32, int nt, int ncol = 0) {
+BigShape big_shape(int n, bool fp32, int nt, int ncol = 0, int rows = 0) {
     BigShape s;
     const int ve = fp32 ? 4 : 2;
     if (ncol < n) ncol = n;
@@ -155,7 +155,7 @@ BigShape big_shape(int n, bool fp32, int nt, int ncol = 0) {
     if (tpr > nt) tpr = nt;
     s.tpr = tpr;
     const int rg = nt / tpr;
-    int R = env_int("GJ_BIG_ROWS", 0);
+    int R = rows > 0 ? rows : env_int("GJ_BIG_ROWS", 0);
     if (R <= 0 && te) R = te->rows;
     if (R <= 0) R = std::max(1, n / 512);
     // a work unit of the step kernel is one register group (2 rows per
@@ -372,11 +372,27 @@ size_t refined_ws(int n, bool acc);
 
 // ------------------------------------------------ blocked elimination
 // Panels of kBlkNb steps on the trailing block, then the delayed updates as
-// FP64 matrix-core products (blocked.hip).  The array's row stride covers
+// FP64 matrix-core products (blocked.hip).  Measured on MI355X (ms per
+// inversion, 4096^2 / 8192^2 FP64, rows per workgroup m / 256): 128-step
+// panels 109.6 / 721.8, 256-step panels 107.9 / 712.8.  The array's row stride covers
 // every panel's row shape from its block's first column (a block of order m
 // at column k0 sweeps k0 + ldw(m) columns); two arrays alternate, one
 // panel's pivot-ordered copy being the next one's input.
-constexpr int kBlkNb = 128;
+constexpr int kBlkNb = 256;
+
+// Row shape of a panel's trailing block of order m.  The table's rows were
+// tuned on whole inversions (up to 1024 on packed batches); for the trailing
+// blocks, rows per workgroup m / kBlkRowDiv measured better (at least one
+// register group; the kernel rounds to whole work units).  ms per 4096^2 /
+// 8192^2 inversion with 128-step panels: m / 256 109.6 / 721.8, m / 512
+// 120.2 / 734.9, m / 1024 139.0 / 799.6, the table's rows 117.9 / 731.8.
+constexpr int kBlkRowDiv = 256;
+BigShape blk_shape(int m) {
+    const int div = env_int("GJ_BLK_RDIV", kBlkRowDiv);   // experiments
+    int rows = 1;
+    while (rows * 2 <= m / std::max(div, 1)) rows *= 2;
+    return big_shape(m, false, big_threads(m, false), 0, env_int("GJ_BIG_ROWS", 0) > 0 ? 0 : rows);
+}
 
 struct BlkLayout {
     BigBufs bb;      // streaming buffers (W: the first array), sized for the largest panel
@@ -393,7 +409,7 @@ BlkLayout blk_layout(int n) {
     int nblk = 1;
     for (int k0 = 0; k0 < n; k0 += L.nb) {
         const int m = n - k0;
-        const BigShape s = big_shape(m, false, big_threads(m, false));
+        const BigShape s = blk_shape(m);
         ldw = std::max<int64_t>(ldw, k0 + s.ldw);
         nblk = std::max(nblk, s.nblk);
     }
@@ -431,8 +447,8 @@ gj_status run_blocked(int n, const double *A, int64_t lda, double *X, int64_t ld
     int cur = 0;
     for (int k0 = 0; k0 < n; k0 += L.nb) {
         const int m = n - k0, nbp = std::min(L.nb, m);
-        const int nt = big_threads(m, false);
-        const BigShape sh = big_shape(m, false, nt);
+        const BigShape sh = blk_shape(m);
+        const int nt = sh.nt;
         // the block's row shape and candidate list fit the layout
         if (k0 + sh.ldw > ldw || sh.nblk > L.nblk) return GJ_E_WORKSPACE;
         BigDesc d = make_desc(sh, L.bb, w, A, lda, X, ldx, ipiv, jpiv, res);

@@ -124,20 +124,34 @@ blk_finish(const BigHdr *__restrict__ hdr, const StepRec *__restrict__ steps, in
             jpiv[x] = -1;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        if (status == 0) {
-            DetAcc<double> det;
-            det.init();
-            for (int k = 0; k < n; ++k) {
-                const StepRec s = steps[k];
-                det.mul(s.p);
-                if (s.rlog != k) det.sign = -det.sign;
-                if (s.clog != k) det.sign = -det.sign;
-            }
-            write_result_ok(res, n, det);
-        } else {
-            write_result_fail(res, status, rank);
+    if (blockIdx.x != 0) return;
+    // the product runs on one thread in step order; the records pass through
+    // LDS in chunks, so that it does not wait on global memory at every step
+    constexpr int kChunk = 1024;
+    __shared__ double s_p[kChunk];
+    __shared__ int s_flip[kChunk];
+    DetAcc<double> det;
+    det.init();
+    for (int b0 = 0; status == 0 && b0 < n; b0 += kChunk) {
+        const int cnt = min(kChunk, n - b0);
+        for (int y = threadIdx.x; y < cnt; y += 256) {
+            const StepRec s = steps[b0 + y];
+            s_p[y] = s.p;
+            s_flip[y] = (s.rlog != b0 + y) ^ (s.clog != b0 + y);
         }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int y = 0; y < cnt; ++y) {
+                det.mul(s_p[y]);
+                if (s_flip[y]) det.sign = -det.sign;
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (status == 0)
+            write_result_ok(res, n, det);
+        else
+            write_result_fail(res, status, rank);
     }
 }
 
