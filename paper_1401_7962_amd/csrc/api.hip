@@ -385,7 +385,9 @@ constexpr int kBlkNb = 256;
 // blocks, rows per workgroup m / kBlkRowDiv measured better (at least one
 // register group; the kernel rounds to whole work units).  ms per 4096^2 /
 // 8192^2 inversion with 128-step panels: m / 256 109.6 / 721.8, m / 512
-// 120.2 / 734.9, m / 1024 139.0 / 799.6, the table's rows 117.9 / 731.8.
+// 120.2 / 734.9, m / 1024 139.0 / 799.6, the table's rows 117.9 / 731.8;
+// with 256-step panels: m / 256 108.0 / 715.1, m / 128 128.7 / 739.1, the
+// table's rows above m = 2048 (m / 256 below) 107.5 / 713.3.
 constexpr int kBlkRowDiv = 256;
 BigShape blk_shape(int m) {
     const int div = env_int("GJ_BLK_RDIV", kBlkRowDiv);   // experiments
