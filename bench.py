@@ -567,9 +567,9 @@ def main():
                     help="run one secondary workload alone and print its result (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the batched and single-matrix paths shard by matrix or by row block across "
-              "GPUs as described in DESIGN.md, but no multi-GPU run is part of it.",
+        print(f"bench.py: measures one GPU only (asked for --gpus {args.gpus}); "
+              "the batched and single-matrix paths would shard by matrix or by row block across "
+              "GPUs, but no multi-GPU run is implemented.",
               file=sys.stderr)
         sys.exit(2)
     import torch

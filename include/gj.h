@@ -55,7 +55,7 @@ typedef enum {
     GJ_E_INVALID_ARG = -1,  /* n < 1, ld < n, NULL pointer, overlap, bad option */
     GJ_E_WORKSPACE = -2,    /* ws_bytes smaller than gj_workspace_size() or misaligned */
     GJ_E_HIP = -3,          /* a HIP runtime call or launch failed */
-    GJ_E_UNSUPPORTED = -4   /* size or option outside what this build handles */
+    GJ_E_UNSUPPORTED = -4   /* size or option combination the library does not handle */
 } gj_status;
 
 /* Per-matrix outcome (gj_result.code). */

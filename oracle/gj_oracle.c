@@ -22,7 +22,7 @@
  *   - a pivot that is null or below a preset zero threshold, when no other
  *     candidate is usable, means A is singular                 (Obs. 2)
  *
- * Readings of points the paper leaves open (each listed in the design doc):
+ * Readings of points the paper leaves open:
  *   - the D half is stored in place in the columns that A no longer needs, so
  *     one n x n array holds [A|D] (the work-skipping form, eqs. 3-10);
  *   - eq. 14 uses correctly rounded division; the pivot slot becomes 1/p;

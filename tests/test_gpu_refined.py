@@ -1,6 +1,6 @@
 """GPU parity for the FP32-elimination + FP64-refinement path.
 
-Bars (tolerances derived in the design doc):
+Bars (each tolerance follows from the arithmetic of its stage):
 * the FP32 elimination is the oracle's FP32 model operation for operation, so
   the returned pivot sequence equals the FP32 oracle's bit for bit;
 * for cond <= 1e4 the refined inverse is within 1e-12 (relative Frobenius) of
