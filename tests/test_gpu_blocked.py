@@ -158,3 +158,19 @@ def test_blocked_headline_size(gj):
     R = Xb[rows] @ A
     R[np.arange(16), rows] -= 1.0
     assert np.abs(R).max() <= 1e-12
+
+
+def test_blocked_with_residual(gj):
+    """want_resid with delayed updates: the residual's workspace follows the
+    blocked layout, and the reported ||A X - I||_F / (||A||_F ||X||_F) is the
+    returned X's."""
+    import torch
+    n = 300
+    A = inputs.conditioned(n, 1e3, inputs.rng_for(0, 7600))
+    opts = gj.make_opts(flags=gj.GJ_FLAG_BLOCKED, want_resid=True)
+    X, _, _, res = gj.gj_invert(torch.from_numpy(A).to("cuda"), opts=opts)
+    torch.cuda.synchronize()
+    r = gj.results_to_dicts(res)[0]
+    assert r["code"] == 0
+    want = oracle.residual(A, X.cpu().numpy())
+    assert abs(r["resid"] - want) <= 1e-2 * want + 1e-18
