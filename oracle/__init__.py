@@ -59,7 +59,7 @@ def build(force: bool = True) -> str:
     """Compile liboracle.so with gcc (no contraction, no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
@@ -97,6 +97,18 @@ def _load():
         lib.ora_lu_static_det_f64.argtypes = [ctypes.c_int, P, ctypes.c_int64, P, P,
                                               ctypes.POINTER(OraResult)]
         lib.ora_lu_static_det_f64.restype = ctypes.c_int
+        lib.ora_gj_invert_f64_par.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P,
+                                              P, P, ctypes.POINTER(OraResult), ctypes.c_int,
+                                              ctypes.c_int]
+        lib.ora_gj_invert_f64_par.restype = ctypes.c_int
+        lib.ora_gj_invert_f32_par.argtypes = lib.ora_gj_invert_f64_par.argtypes
+        lib.ora_gj_invert_f32_par.restype = ctypes.c_int
+        lib.ora_gj_invert_f80_par.argtypes = [ctypes.c_int, P, ctypes.c_int64, ctypes.c_double, P,
+                                              P, P, ctypes.POINTER(OraResult), ctypes.c_int]
+        lib.ora_gj_invert_f80_par.restype = ctypes.c_int
+        lib.ora_gj_invert_batched.argtypes = [ctypes.c_int, P, P, P, P, P, P, P, P,
+                                              ctypes.c_double, ctypes.c_int, ctypes.c_int]
+        lib.ora_gj_invert_batched.restype = ctypes.c_int
         lib.ora_result_size.restype = ctypes.c_int
         assert lib.ora_result_size() == ctypes.sizeof(OraResult)
         _lib = lib
@@ -143,6 +155,97 @@ def gj_invert_rule_f64(A, rule: int, zero_tol: float = -1.0):
     _load().ora_gj_invert_f64_rule(n, _ptr(A), n, float(zero_tol), int(rule), _ptr(X), _ptr(ipiv),
                                    _ptr(jpiv), ctypes.byref(res))
     return X, ipiv, jpiv, res.as_dict()
+
+
+def host_threads() -> int:
+    """Host cores this process may run on, capped by OMP_NUM_THREADS when set."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def gj_invert_f64_par(A, nthreads: int | None = None, zero_tol: float = -1.0,
+                      max_steps: int | None = None):
+    """The FP64 oracle with each step's row work shared among ``nthreads``
+    OpenMP threads (bitwise the serial result).  ``max_steps`` < n stops
+    after that many steps with no depivoting (a timing sample).  Returns
+    (X, ipiv, jpiv, result dict)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    X = np.empty((n, n))
+    ipiv = np.full(n, -1, dtype=np.int32)
+    jpiv = np.full(n, -1, dtype=np.int32)
+    res = OraResult()
+    code = _load().ora_gj_invert_f64_par(n, _ptr(A), n, float(zero_tol), _ptr(X), _ptr(ipiv),
+                                         _ptr(jpiv), ctypes.byref(res),
+                                         int(nthreads or host_threads()),
+                                         n if max_steps is None else int(max_steps))
+    if code < 0:
+        raise MemoryError("oracle: allocation failed")
+    return X, ipiv, jpiv, res.as_dict()
+
+
+def gj_invert_f32_par(A, nthreads: int | None = None, zero_tol: float = 0.0):
+    """The FP32 model on ``nthreads`` threads (bitwise the serial FP32 model)."""
+    A = np.ascontiguousarray(A, dtype=np.float32)
+    n = A.shape[0]
+    X = np.empty((n, n), dtype=np.float32)
+    ipiv = np.full(n, -1, dtype=np.int32)
+    jpiv = np.full(n, -1, dtype=np.int32)
+    res = OraResult()
+    code = _load().ora_gj_invert_f32_par(n, _ptr(A), n, float(zero_tol), _ptr(X), _ptr(ipiv),
+                                         _ptr(jpiv), ctypes.byref(res),
+                                         int(nthreads or host_threads()), n)
+    if code < 0:
+        raise MemoryError("oracle: allocation failed")
+    return X, ipiv, jpiv, res.as_dict()
+
+
+def gj_invert_f80_par(A, nthreads: int | None = None, zero_tol: float = -1.0):
+    """The long-double oracle on ``nthreads`` threads (bitwise the serial
+    long-double result)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    X = np.empty((n, n))
+    ipiv = np.full(n, -1, dtype=np.int32)
+    jpiv = np.full(n, -1, dtype=np.int32)
+    res = OraResult()
+    code = _load().ora_gj_invert_f80_par(n, _ptr(A), n, float(zero_tol), _ptr(X), _ptr(ipiv),
+                                         _ptr(jpiv), ctypes.byref(res),
+                                         int(nthreads or host_threads()))
+    if code < 0:
+        raise MemoryError("oracle: allocation failed")
+    return X, ipiv, jpiv, res.as_dict()
+
+
+def gj_invert_batched(sizes, offs, packed, nthreads: int | None = None, zero_tol: float = -1.0,
+                      fp32: bool = False):
+    """One serial oracle run per member of a packed batch (member b: order
+    sizes[b] at packed[offs[b]:], ld sizes[b]), members shared among
+    ``nthreads`` OpenMP threads.  ``fp32``: the FP32 model instead of FP64.
+    Returns (X packed like the input, ipiv, jpiv (concatenated in member
+    order), list of result dicts)."""
+    sizes = np.ascontiguousarray(sizes, dtype=np.int32)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    packed = np.ascontiguousarray(packed, dtype=np.float64)
+    batch = len(sizes)
+    if batch and int(offs[-1]) + int(sizes[-1]) ** 2 > packed.size:
+        raise ValueError("packed buffer too short for the last member")
+    poff = np.zeros(batch, dtype=np.int64)
+    poff[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
+    X = np.full(packed.size, np.nan)
+    ipiv = np.full(int(sizes.sum()), -1, dtype=np.int32)
+    jpiv = np.full(int(sizes.sum()), -1, dtype=np.int32)
+    res = (OraResult * max(batch, 1))()
+    code = _load().ora_gj_invert_batched(batch, _ptr(sizes), _ptr(offs), _ptr(packed), _ptr(X),
+                                         _ptr(poff), _ptr(ipiv), _ptr(jpiv), res,
+                                         float(zero_tol), 1 if fp32 else 0,
+                                         int(nthreads or host_threads()))
+    if code < 0:
+        raise MemoryError("oracle: allocation failed")
+    return X, ipiv, jpiv, [res[b].as_dict() for b in range(batch)]
 
 
 def gj_invert_f32(A, zero_tol: float = 0.0):
@@ -229,12 +332,17 @@ def residual(A, X) -> float:
 def newton_schulz(A, X0, max_iters: int = 10, stall: float = 0.5, accept: float = 1e-2):
     """Newton-Schulz refinement X <- X + X (I - A X) in FP64.
 
-    The loop: R = I - A X.  An update is kept only if ||R||_F decreases;
-    once ||R||_F < 1 (where R_{k+1} = R_k^2 contracts quadratically), an
-    update that does not bring it below ``stall`` times the previous value
-    means the FP64 rounding floor is reached and the loop ends.  At most
-    ``max_iters`` updates.  The result is accepted when its final ||R||_F is
-    at most ``accept``; otherwise the caller falls back to the plain FP64 run.
+    The loop: R = I - A X.  An update is kept only if ||R||_F decreases.
+    In exact arithmetic an update squares the residual (I - A (X + X R) =
+    R^2), so ||R_{k+1}||_F <= ||R_k||_F^2.  The FP64 rounding floor is
+    recognised as a kept update that contracted neither by the factor
+    ``stall`` nor to within twice that quadratic bound, rn > max(stall r,
+    2 r^2); the loop ends there.  For r >= 1/2 the bound 2 r^2 is at least r,
+    so the loop goes on for as long as the norm falls, however slowly (a
+    residual above 1 can still converge when the spectral radius of R is
+    below 1).  At most ``max_iters`` updates.  The result is accepted when
+    its final ||R||_F is at most ``accept``; otherwise the caller falls back
+    to the plain FP64 run.
     Returns (X, updates kept, [||R_k||_F for every R computed], accepted).
     """
     A = np.asarray(A, dtype=np.float64)
@@ -256,7 +364,7 @@ def newton_schulz(A, X0, max_iters: int = 10, stall: float = 0.5, accept: float 
             prev = r
             X, R, r = Xn, Rn, rn
             updates = it
-            if rn == 0.0 or (prev < 1.0 and rn > stall * prev):
+            if rn == 0.0 or rn > max(stall * prev, 2.0 * prev * prev):
                 break                      # the rounding floor is reached
     accepted = bool(np.isfinite(r) and r <= accept)
     return X, updates, norms, accepted

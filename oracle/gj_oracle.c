@@ -39,9 +39,10 @@
  * FP64 oracle), long double (x87 64-bit mantissa: the "truth" used for
  * forward errors) and float (a CPU model of an FP32 elimination).
  *
- * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fPIC -shared
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -fPIC -shared
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -261,9 +262,204 @@ static int isfin_f(float v) { return isfinite(v); }
 GJ_INPLACE(ora_gj_invert_f64, double, fabs, fma, frexp, isfin_d, 0x1p-52)
 GJ_INPLACE(ora_gj_invert_f32, float, fabsf, fmaf, frexpf, isfin_f, 0.0)
 
+/*
+ * The same elimination (full search only) with the independent work of each
+ * step shared among `nthreads` OpenMP threads, so that the oracle can be timed
+ * on every host core.  Nothing about the arithmetic changes:
+ *   - the search splits rows k..n-1 into contiguous ranges, one per thread;
+ *     each range keeps its first maximum in row-major order, and the ranges
+ *     are merged in row order with the same strict '>', which gives the first
+ *     maximum of the whole block -- the serial winner;
+ *   - eq. 15 updates each row i != k on its own (every row reads only the
+ *     pivot row, which no thread writes during the update);
+ *   - swaps, the pivot, the determinant and the depivoting stay serial.
+ * So X, the pivots and the determinant equal the serial function's bit for
+ * bit (a test checks it).  `max_steps` < n stops after that many steps
+ * without depivoting, as the _first_steps form does (used to time a sample).
+ */
+#define GJ_INPLACE_PAR(NAME, T, FABS, FMA, FREXP, ISFIN, EPS_DEFAULT)              \
+int NAME(int n, const T *A, int64_t lda, double zero_tol, T *X, int32_t *ipiv,     \
+         int32_t *jpiv, ora_result *res, int nthreads, int max_steps)              \
+{                                                                                  \
+    if (nthreads < 1) nthreads = 1;                                                \
+    T *sb = (T *)malloc(sizeof(T) * (size_t)nthreads);                             \
+    int *sr = (int *)malloc(sizeof(int) * (size_t)nthreads * 3);                   \
+    if (!sb || !sr) { free(sb); free(sr); return -1; }                             \
+    T *W = X;                                                                      \
+    _Pragma("omp parallel for num_threads(nthreads) schedule(static)")            \
+    for (int i = 0; i < n; ++i)                                                    \
+        for (int j = 0; j < n; ++j)                                                \
+            W[(int64_t)i * n + j] = A[(int64_t)i * lda + j];   /* eqs. 1-2 */      \
+    int sign = 1;                                                                  \
+    T m_acc = (T)1;                                                                \
+    int64_t e_acc = 0;                                                             \
+    T tau = (T)zero_tol;                                                           \
+    res->refine_iters = 0;                                                         \
+    res->resid = NAN;                                                              \
+    for (int k = 0; k < n; ++k) {                                                  \
+        if (k == max_steps) { free(sb); free(sr); return ORA_OK; }                 \
+        int used = 1;                                                              \
+        _Pragma("omp parallel num_threads(nthreads)")                              \
+        {                                                                          \
+            const int id = omp_get_thread_num(), cnt = omp_get_num_threads();     \
+            const int64_t rows = n - k;                                            \
+            const int lo = k + (int)(rows * id / cnt);                             \
+            const int hi = k + (int)(rows * (id + 1) / cnt);                       \
+            T best = (T)-1;                                                        \
+            int r = -1, c = -1, nonfinite = 0;                                     \
+            for (int i = lo; i < hi; ++i)                                          \
+                for (int j = k; j < n; ++j) {                                      \
+                    T v = FABS(W[(int64_t)i * n + j]);                             \
+                    if (!ISFIN(v)) nonfinite = 1;                                  \
+                    if (v > best) { best = v; r = i; c = j; }                      \
+                }                                                                  \
+            sb[id] = best;                                                         \
+            sr[3 * id] = r; sr[3 * id + 1] = c; sr[3 * id + 2] = nonfinite;        \
+            if (id == 0) used = cnt;                                               \
+        }                                                                          \
+        /* merge in row order: strict '>' keeps the earliest range's maximum */   \
+        T best = (T)-1;                                                            \
+        int r = -1, c = -1, nonfinite = 0;                                         \
+        for (int id = 0; id < used; ++id) {                                        \
+            nonfinite |= sr[3 * id + 2];                                           \
+            if (sb[id] > best) { best = sb[id]; r = sr[3 * id]; c = sr[3 * id + 1]; } \
+        }                                                                          \
+        if (nonfinite) {                                                           \
+            ora_fill_failure(res, ORA_NONFINITE, k, n, ipiv, jpiv);                \
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) W[t] = (T)NAN;            \
+            free(sb); free(sr);                                                    \
+            return ORA_NONFINITE;                                                  \
+        }                                                                          \
+        if (k == 0 && zero_tol < 0) tau = (T)n * (T)(EPS_DEFAULT) * best;          \
+        if (best == (T)0 || best < tau) {                                          \
+            ora_fill_failure(res, ORA_SINGULAR, k, n, ipiv, jpiv);                 \
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) W[t] = (T)NAN;            \
+            free(sb); free(sr);                                                    \
+            return ORA_SINGULAR;                                                   \
+        }                                                                          \
+        ipiv[k] = r;                                                               \
+        jpiv[k] = c;                                                               \
+        if (r != k) {                                                              \
+            for (int j = 0; j < n; ++j) {                                          \
+                T t = W[(int64_t)k * n + j];                                       \
+                W[(int64_t)k * n + j] = W[(int64_t)r * n + j];                     \
+                W[(int64_t)r * n + j] = t;                                         \
+            }                                                                      \
+            sign = -sign;                                                          \
+        }                                                                          \
+        if (c != k) {                                                              \
+            for (int i = 0; i < n; ++i) {                                          \
+                T t = W[(int64_t)i * n + k];                                       \
+                W[(int64_t)i * n + k] = W[(int64_t)i * n + c];                     \
+                W[(int64_t)i * n + c] = t;                                         \
+            }                                                                      \
+            sign = -sign;                                                          \
+        }                                                                          \
+        T p = W[(int64_t)k * n + k];                                               \
+        {                                                                          \
+            int e1, e2;                                                            \
+            T f = FREXP(p, &e1);                                                   \
+            m_acc = m_acc * f;                                                     \
+            e_acc += e1;                                                           \
+            m_acc = FREXP(m_acc, &e2);                                             \
+            e_acc += e2;                                                           \
+        }                                                                          \
+        W[(int64_t)k * n + k] = (T)1;                               /* eq. 14 */  \
+        for (int j = 0; j < n; ++j)                                                \
+            W[(int64_t)k * n + j] = W[(int64_t)k * n + j] / p;                     \
+        _Pragma("omp parallel for num_threads(nthreads) schedule(static)")        \
+        for (int i = 0; i < n; ++i) {                               /* eq. 15 */  \
+            if (i == k) continue;                                                  \
+            T q = W[(int64_t)i * n + k];                                           \
+            W[(int64_t)i * n + k] = (T)0;                                          \
+            for (int j = 0; j < n; ++j)                                            \
+                W[(int64_t)i * n + j] = FMA(-q, W[(int64_t)k * n + j],             \
+                                            W[(int64_t)i * n + j]);                \
+        }                                                                          \
+    }                                                                              \
+    free(sb);                                                                      \
+    free(sr);                                                                      \
+    for (int k = n - 1; k >= 0; --k) {                               /* Obs. 3 */  \
+        int r = ipiv[k], c = jpiv[k];                                              \
+        if (r != k)                                                                \
+            for (int i = 0; i < n; ++i) {                                          \
+                T t = W[(int64_t)i * n + k];                                       \
+                W[(int64_t)i * n + k] = W[(int64_t)i * n + r];                     \
+                W[(int64_t)i * n + r] = t;                                         \
+            }                                                                      \
+        if (c != k)                                                                \
+            for (int j = 0; j < n; ++j) {                                          \
+                T t = W[(int64_t)k * n + j];                                       \
+                W[(int64_t)k * n + j] = W[(int64_t)c * n + j];                     \
+                W[(int64_t)c * n + j] = t;                                         \
+            }                                                                      \
+    }                                                                              \
+    res->code = ORA_OK;                                                            \
+    res->rank = n;                                                                 \
+    res->det_sign = (m_acc < 0) ? -sign : sign;                                    \
+    res->det_mant = (double)FABS(m_acc);                                           \
+    res->det_exp = e_acc;                                                          \
+    res->det = ora_ldexp64((double)sign * (double)m_acc, e_acc);                   \
+    res->logabsdet = log(res->det_mant) + (double)e_acc * 0.69314718055994530942;  \
+    return ORA_OK;                                                                 \
+}
+
+GJ_INPLACE_PAR(ora_gj_invert_f64_par, double, fabs, fma, frexp, isfin_d, 0x1p-52)
+GJ_INPLACE_PAR(ora_gj_invert_f32_par, float, fabsf, fmaf, frexpf, isfin_f, 0.0)
+GJ_INPLACE_PAR(ora_gj_invert_f80_par_impl, long double, fabsl, fmal, frexpl, isfin_l, 0x1p-52)
+
+/*
+ * Many independent matrices, one serial oracle run each, shared among
+ * `nthreads` OpenMP threads (dynamic schedule).  Member b: order n[b], input
+ * at A + off[b] (ld n[b]), inverse at X + off[b] (ld n[b]), pivots at
+ * ipiv/jpiv + piv_off[b], record res[b].  precision 0: the FP64 oracle;
+ * 1: the FP32 model (input rounded to float, result widened back).
+ */
+int ora_gj_invert_batched(int batch, const int32_t *nn, const int64_t *off, const double *A,
+                          double *X, const int64_t *piv_off, int32_t *ipiv, int32_t *jpiv,
+                          ora_result *res, double zero_tol, int precision, int nthreads)
+{
+    if (nthreads < 1) nthreads = 1;
+    int failed = 0;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1) reduction(| : failed)
+    for (int b = 0; b < batch; ++b) {
+        const int n = nn[b];
+        if (precision == 0) {
+            ora_gj_invert_f64(n, A + off[b], n, zero_tol, X + off[b], ipiv + piv_off[b],
+                              jpiv + piv_off[b], &res[b]);
+        } else {
+            float *a = (float *)malloc(sizeof(float) * (size_t)n * n);
+            float *x = (float *)malloc(sizeof(float) * (size_t)n * n);
+            if (!a || !x) { failed = 1; free(a); free(x); continue; }
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) a[t] = (float)A[off[b] + t];
+            ora_gj_invert_f32(n, a, n, zero_tol, x, ipiv + piv_off[b], jpiv + piv_off[b], &res[b]);
+            for (int64_t t = 0; t < (int64_t)n * n; ++t) X[off[b] + t] = (double)x[t];
+            free(a);
+            free(x);
+        }
+    }
+    return failed ? -1 : 0;
+}
+
 /* long double variant: input and output in double, arithmetic in long
  * double.  Used as the "truth" for forward errors (unit roundoff 2^-64). */
 GJ_INPLACE(ora_gj_invert_f80_impl, long double, fabsl, fmal, frexpl, isfin_l, 0x1p-52)
+
+/* the long-double run on `nthreads` threads (same results as the serial one) */
+int ora_gj_invert_f80_par(int n, const double *A, int64_t lda, double zero_tol, double *X,
+                          int32_t *ipiv, int32_t *jpiv, ora_result *res, int nthreads)
+{
+    long double *a = (long double *)malloc(sizeof(long double) * (size_t)n * n);
+    long double *x = (long double *)malloc(sizeof(long double) * (size_t)n * n);
+    if (!a || !x) { free(a); free(x); return -1; }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) a[(int64_t)i * n + j] = A[(int64_t)i * lda + j];
+    int code = ora_gj_invert_f80_par_impl(n, a, n, zero_tol, x, ipiv, jpiv, res, nthreads, n);
+    for (int64_t t = 0; t < (int64_t)n * n; ++t) X[t] = (double)x[t];
+    free(a);
+    free(x);
+    return code;
+}
 
 int ora_gj_invert_f80(int n, const double *A, int64_t lda, double zero_tol, double *X,
                       int32_t *ipiv, int32_t *jpiv, ora_result *res)

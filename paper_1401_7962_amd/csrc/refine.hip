@@ -4,10 +4,12 @@
 //    threshold 0): X0, the pivot sequence, and half the HBM traffic.
 // 2. Newton-Schulz in FP64 on the matrix cores:
 //        R_k = I - A X_k,   X_{k+1} = X_k + X_k R_k   (so R_{k+1} = R_k^2),
-//    with the guard: an update is kept only if ||R||_F decreases, and once
-//    ||R||_F < 1 the loop ends at the first update that fails to halve it
-//    (the FP64 rounding floor), or after max_refine_iters updates.  A result whose final ||R||_F exceeds
-//    1e-2 is replaced by the plain FP64 elimination (GJ_RES_REFINE_FALLBACK).
+//    with the guard: an update is kept only if ||R||_F decreases, and the
+//    loop ends at the FP64 rounding floor, recognised as a kept update that
+//    contracted neither by half nor to within twice the quadratic bound
+//    ||R_{k+1}|| <= ||R_k||^2 (rn > max(r/2, 2 r^2)), or after
+//    max_refine_iters updates.  A result whose final ||R||_F exceeds 1e-2 is
+//    replaced by the plain FP64 elimination (GJ_RES_REFINE_FALLBACK).
 // 3. The FP64 determinant, which FP32 pivots cannot give: A is permuted with
 //    the FP32 run's row and column order, and block Gaussian elimination in
 //    FP64 runs over diagonal blocks of at most 128: each diagonal block of the
@@ -94,9 +96,11 @@ refine_after_update_kernel(RefineCtl *ctls, int it, int max_iters, double stall)
     ctl->r = rn;
     ctl->updates = it;
     ctl->final_buf = it & 1;
-    // the halving test means "rounding floor reached" only in the contraction
-    // regime ||R|| < 1, where ||R_{k+1}|| <= ||R_k||^2
-    if ((r < 1.0 && rn > stall * r) || it >= max_iters || rn == 0.0) ctl->run_ns = 0;
+    // rounding floor: the update contracted neither by the factor `stall` nor
+    // to within twice the quadratic bound ||R_{k+1}|| <= ||R_k||^2.  For
+    // r >= 1/2 the bound is no contraction at all, so the loop then goes on
+    // while the norm falls, however slowly.
+    if (rn > fmax(stall * r, 2.0 * r * r) || it >= max_iters || rn == 0.0) ctl->run_ns = 0;
 }
 
 __global__ void refine_finish_kernel(RefineCtl *ctls, int count, double accept, int det_wanted) {

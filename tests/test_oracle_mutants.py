@@ -40,7 +40,7 @@ def _build(tmp_path, name, old, new):
     c = tmp_path / f"{name}.c"
     so = tmp_path / f"{name}.so"
     c.write_text(mutated)
-    subprocess.run(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
                     "-o", str(so), str(c), "-lm"], check=True)
     lib = ctypes.CDLL(str(so))
     fn = lib.ora_gj_invert_f64
@@ -138,7 +138,7 @@ def _build_solve(tmp_path, name, old, new):
     c = tmp_path / f"{name}.c"
     so = tmp_path / f"{name}.so"
     c.write_text(src.replace(old, new))
-    subprocess.run(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
                     "-o", str(so), str(c), "-lm"], check=True)
     fn = ctypes.CDLL(str(so)).ora_gj_solve_f64
     P = ctypes.c_void_p
@@ -212,7 +212,7 @@ def _build_rule(tmp_path, name, old, new):
     c = tmp_path / f"{name}.c"
     so = tmp_path / f"{name}.so"
     c.write_text(src.replace(old, new))
-    subprocess.run(["gcc", "-O1", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
                     "-o", str(so), str(c), "-lm"], check=True)
     fn = ctypes.CDLL(str(so)).ora_gj_invert_f64_rule
     P = ctypes.c_void_p
@@ -264,3 +264,65 @@ def test_rule_mutant_is_caught(tmp_path, name):
     old, new = RULE_MUTANTS[name]
     fn = _build_rule(tmp_path, name, old, new)
     assert _rule_battery(fn), f"mutant {name} passed every pin"
+
+
+# Planted mistakes in the Newton-Schulz stopping rule (Python source of
+# oracle.newton_schulz, rewritten and re-executed).  The exact diagonal pins
+# of test_oracle_pins.py must reject each one.
+NS_MUTANTS = {
+    # the floor test applied whenever ||R|| < 1 (halving only)
+    "halving_below_one": ("rn > max(stall * prev, 2.0 * prev * prev)",
+                          "(prev < 1.0 and rn > stall * prev)"),
+    # the floor test applied at any norm, above 1 too
+    "halving_above_one": ("rn > max(stall * prev, 2.0 * prev * prev)", "rn > stall * prev"),
+    # a much stricter acceptance threshold
+    "accept_1e-6": ("accepted = bool(np.isfinite(r) and r <= accept)",
+                    "accepted = bool(np.isfinite(r) and r <= 1e-6)"),
+    # a rejected update replaces the iterate anyway
+    "keep_failed_update": ("if not rn < r:\n                break",
+                           "if not rn < r:\n                X, R, r = Xn, Rn, rn\n                break"),
+}
+
+
+def _ns_mutant(name):
+    import inspect
+    import textwrap
+    old, new = NS_MUTANTS[name]
+    src = textwrap.dedent(inspect.getsource(oracle.newton_schulz))
+    assert old in src, f"mutation anchor for {name} not found"
+    ns = {"np": np}
+    exec(compile(src.replace(old, new), f"<ns mutant {name}>", "exec"), ns)
+    return ns["newton_schulz"]
+
+
+def _ns_battery(fn):
+    """The exact diagonal cases of the stopping-rule pins; returns the failing ones."""
+    failed = []
+
+    def case(e, d, max_iters=10):
+        A = np.diag(np.asarray(d, dtype=np.float64))
+        X0 = np.diag((1.0 - np.asarray(e)) / np.asarray(d, dtype=np.float64))
+        return fn(A, X0, max_iters=max_iters)
+
+    _, u, norms, acc = case([0.875], [2.0])
+    if not (u == 9 and acc and norms[-1] == 0.0):
+        failed.append("slow_start_below_one")
+    _, u, norms, acc = case([0.875] * 16, [4.0] * 16)
+    if not (u == 9 and acc and norms[-1] == 0.0):
+        failed.append("slow_fall_above_one")
+    _, u, norms, acc = case([0.5], [1.0], max_iters=3)
+    if not (u == 3 and acc):
+        failed.append("accept_threshold")
+    X, u, norms, acc = fn(np.diag([4.0]), np.diag([0.5]))
+    if not (u == 0 and X[0, 0] == 0.5):
+        failed.append("no_progress")
+    return failed
+
+
+def test_unmutated_newton_schulz_passes_battery():
+    assert _ns_battery(oracle.newton_schulz) == []
+
+
+@pytest.mark.parametrize("name", sorted(NS_MUTANTS))
+def test_newton_schulz_mutant_is_caught(name):
+    assert _ns_battery(_ns_mutant(name)), f"mutant {name} passed every stopping-rule pin"

@@ -419,6 +419,61 @@ def test_newton_schulz_squares_the_residual(cond):
     assert err_ns <= 2 * max(err_or, 1e-14)
 
 
+def _ns_diag_case(e, d, max_iters=10):
+    """A = diag(d), X0 = diag((1 - e_i) / d_i): R_0 = I - A X0 = diag(e_i),
+    and each update squares it, R_k = diag(e_i^(2^k)).  With d_i powers of
+    two and e_i dyadic, every operation is exact until 1 - e_i^(2^k) needs
+    more than 53 bits; R becomes exactly 0 once e_i^(2^k) < 2^-54 (1 - e
+    then rounds to 1)."""
+    A = np.diag(np.asarray(d, dtype=np.float64))
+    X0 = np.diag((1.0 - np.asarray(e, dtype=np.float64)) / np.asarray(d, dtype=np.float64))
+    return oracle.newton_schulz(A, X0, max_iters=max_iters)
+
+
+def test_newton_schulz_stop_rule_slow_start_below_one():
+    """||R_0||_F = 7/8: the exact norms are (7/8)^(2^k) = 0.875, 0.766, 0.586,
+    0.344, 0.118, 0.0139, 1.9e-4, 3.8e-8, 1.4e-15 (k = 0..8), every kept
+    update within the quadratic bound, and R_9 = 0 exactly ((7/8)^512 <
+    2^-54).  So exactly 9 updates, ending at 0, accepted.  An update from
+    0.875 to 0.766 does not halve the norm: a rule that stops at the first
+    such update below 1 would keep 1 update and fall back."""
+    X, updates, norms, accepted = _ns_diag_case([0.875], [2.0])
+    assert updates == 9 and accepted and norms[-1] == 0.0
+    for k in range(5):                       # exact while (7/8)^(2^k) fits 53 bits
+        assert norms[k] == 0.875 ** (2 ** k)
+    assert X[0, 0] == 0.5                    # the exact inverse
+
+
+def test_newton_schulz_stop_rule_slow_fall_above_one():
+    """Sixteen diagonal entries with e = 7/8: ||R_k||_F = 4 (7/8)^(2^k) =
+    3.5, 3.06, 2.34, 1.37, 0.47, 0.056, 7.8e-4, 1.5e-7, 5.7e-15, then 0:
+    9 updates, accepted, although the first three fall by less than half."""
+    X, updates, norms, accepted = _ns_diag_case([0.875] * 16, [4.0] * 16)
+    assert updates == 9 and accepted and norms[-1] == 0.0
+    assert norms[0] == 3.5 and 3.0 < norms[1] < 3.1
+    assert np.array_equal(X, np.eye(16) / 4.0)
+
+
+def test_newton_schulz_accept_threshold():
+    """e = 1/2: ||R_k|| = 2^-(2^k).  Capped at 3 updates the loop ends at
+    2^-8 <= 1e-2 (accepted); capped at 2 it ends at 2^-4 > 1e-2 (not
+    accepted: the caller falls back to the FP64 elimination)."""
+    _, updates, norms, accepted = _ns_diag_case([0.5], [1.0], max_iters=3)
+    assert updates == 3 and norms == [0.5, 0.25, 0.0625, 2.0 ** -8] and accepted
+    _, updates, norms, accepted = _ns_diag_case([0.5], [1.0], max_iters=2)
+    assert updates == 2 and norms[-1] == 0.0625 and not accepted
+
+
+def test_newton_schulz_no_progress_keeps_previous_iterate():
+    """X0 = 2 A^-1 (A = diag(4)): R_0 = -1, and X1 = X0 + X0 R0 = 0 gives
+    R_1 = I, no decrease: no update is kept and X0 is returned."""
+    A = np.diag([4.0])
+    X0 = np.diag([0.5])
+    X, updates, norms, accepted = oracle.newton_schulz(A, X0)
+    assert updates == 0 and norms == [1.0, 1.0] and not accepted
+    assert X[0, 0] == 0.5
+
+
 def test_pivots_to_permutations():
     A = inputs.rng_for(0, 1300).standard_normal((12, 12))
     X, ipiv, jpiv, _ = oracle.gj_invert_f64(A)
