@@ -16,6 +16,10 @@ that are plain definitions written out in NumPy / Python:
   only library step (parity: pinned by the contraction property
   R_{k+1} = R_k^2 checked in the tests);
 * ``residual`` -- ||A X - I||_F / (||A||_F ||X||_F);
+* ``exact_residual`` / ``inverse_truth`` -- I - A X with the large products
+  formed exactly from bit slices, and Newton steps with it: a reference
+  inverse for forward errors at orders where the long-double elimination is
+  too slow (pinned against that elimination and against exact inverses);
 * ``cofactor_det`` -- exact rational Laplace expansion (n <= 7), the
   brute-force determinant pin;
 * ``gj_solve_f64`` -- the augmented elimination with a general right-hand
@@ -368,6 +372,74 @@ def newton_schulz(A, X0, max_iters: int = 10, stall: float = 0.5, accept: float 
                 break                      # the rounding floor is reached
     accepted = bool(np.isfinite(r) and r <= accept)
     return X, updates, norms, accepted
+
+
+def _slices(M, axis: int, bits: int, parts: int):
+    """M = sum of ``parts`` slices.  Along ``axis`` (1: per row, 0: per
+    column) let 2^e bound the largest |entry|; slice p holds the bits of M
+    from 2^(e - bits p) down to the grid 2^(e - bits (p+1)) (rounded to that
+    grid), so every slice but the last is an integer multiple of its grid with
+    at most ``bits`` + 1 bits; the last slice is what remains.  Every
+    subtraction is exact (a value minus its rounding to a coarser grid)."""
+    amax = np.max(np.abs(M), axis=axis, keepdims=True)
+    _, e = np.frexp(amax)
+    rest = np.array(M, dtype=np.float64, copy=True)
+    out = []
+    for p in range(parts - 1):
+        unit = np.ldexp(1.0, e - bits * (p + 1))
+        S = np.rint(rest / unit) * unit
+        out.append(S)
+        rest = rest - S
+    out.append(rest)
+    return out
+
+
+def exact_residual(A, X, bits: int = 20):
+    """R = I - A X with the large products formed without rounding.
+
+    A is split per row and X per column into three slices (``_slices``).  A
+    product of two leading slices is a sum of n terms that are integer
+    multiples of the two grids' product and at most 2^(2 bits) of them each,
+    so for n <= 2^(53 - 2 bits) (8192 with 20 bits) every partial sum is
+    exact, in any summation order.  I - A0 X0 is exact too (Sterbenz on the
+    diagonal).  The remaining slice products, at most 2^-bits of the leading
+    one, are added from the largest down, each rounding at about u times a
+    partial sum of size 2^-bits: R is accurate to about 2^-bits u |A||X|
+    absolutely, far below the FP64 residual's n u |A||X|.  The products are
+    library matmuls (the only library step)."""
+    A = np.asarray(A, dtype=np.float64)
+    X = np.asarray(X, dtype=np.float64)
+    n = A.shape[0]
+    if n > 2 ** (53 - 2 * bits):
+        raise ValueError("order too large for exact slice products at this slice width")
+    As = _slices(A, 1, bits, 3)
+    Xs = _slices(X, 0, bits, 3)
+    R = np.eye(n) - As[0] @ Xs[0]
+    # remaining products, largest first: (0,1) (1,0), then (1,1) (0,2) (2,0), ...
+    for i, j in sorted(((i, j) for i in range(3) for j in range(3) if i + j > 0),
+                       key=lambda ij: (ij[0] + ij[1], ij)):
+        R = R - As[i] @ Xs[j]
+    return R
+
+
+def inverse_truth(A, X0, max_steps: int = 3):
+    """A reference inverse far more accurate than X0 (an FP64 inverse of A):
+    Newton steps X <- X + X R with R = exact_residual(A, X).  A step from an
+    inverse with relative error e leaves about cond(A) e^2 + u, so from the
+    FP64 oracle's inverse (e ~ cond u) one or two steps reach about u for
+    cond up to 1e8.  Stops when the correction stops shrinking."""
+    X = np.array(X0, dtype=np.float64, copy=True)
+    last = np.inf
+    for _ in range(max_steps):
+        C = X @ exact_residual(A, X)
+        c = float(np.linalg.norm(C))
+        if not c < last:
+            break
+        X = X + C
+        last = c
+        if c <= 1e-17 * float(np.linalg.norm(X)):
+            break
+    return X
 
 
 def cofactor_det(A) -> Fraction:

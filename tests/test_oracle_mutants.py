@@ -326,3 +326,38 @@ def test_unmutated_newton_schulz_passes_battery():
 @pytest.mark.parametrize("name", sorted(NS_MUTANTS))
 def test_newton_schulz_mutant_is_caught(name):
     assert _ns_battery(_ns_mutant(name)), f"mutant {name} passed every stopping-rule pin"
+
+
+# Planted mistakes in the exact residual (Python source of
+# oracle.exact_residual): a dropped slice product, the last slice of A lost,
+# the diagonal's I dropped.
+RESID_MUTANTS = {
+    "dropped_product": ("if i + j > 0)", "if 0 < i + j < 4)"),
+    "remainder_dropped": ("As = _slices(A, 1, bits, 3)", "As = _slices(A, 1, bits, 2) + [0.0 * A]"),
+    "no_identity": ("R = np.eye(n) - As[0] @ Xs[0]", "R = -(As[0] @ Xs[0])"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(RESID_MUTANTS))
+def test_exact_residual_mutant_is_caught(name):
+    import inspect
+    import textwrap
+    from fractions import Fraction
+    old, new = RESID_MUTANTS[name]
+    src = textwrap.dedent(inspect.getsource(oracle.exact_residual))
+    assert old in src, f"mutation anchor for {name} not found"
+    ns = {"np": np, "_slices": oracle._slices}
+    exec(compile(src.replace(old, new), f"<resid mutant {name}>", "exec"), ns)
+    fn = ns["exact_residual"]
+    n = 10
+    A = inputs.conditioned(n, 1e6, inputs.rng_for(0, 1400))
+    X, _, _, _ = oracle.gj_invert_f64(A)
+    R = fn(A, X)
+    worst = Fraction(0)
+    for i in range(n):
+        for j in range(n):
+            exact = Fraction(int(i == j)) - sum(Fraction(float(A[i, k])) * Fraction(float(X[k, j]))
+                                                for k in range(n))
+            if exact != 0:
+                worst = max(worst, abs(Fraction(float(R[i, j])) - exact) / abs(exact))
+    assert worst > Fraction(2, 2 ** 52), f"mutant {name} passed the exact-residual pin"

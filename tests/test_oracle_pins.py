@@ -474,6 +474,46 @@ def test_newton_schulz_no_progress_keeps_previous_iterate():
     assert X[0, 0] == 0.5
 
 
+@pytest.mark.parametrize("cond", [1e2, 1e6, 1e8])
+def test_exact_residual_against_rationals(cond):
+    """I - A X from bit-slice products equals the exact rational residual of
+    the two FP64 matrices, rounded (n = 10; every double is a rational)."""
+    n = 10
+    A = inputs.conditioned(n, cond, inputs.rng_for(0, 1400))
+    X, _, _, _ = oracle.gj_invert_f64(A)
+    R = oracle.exact_residual(A, X)
+    Fa = [[Fraction(float(v)) for v in row] for row in A]
+    Fx = [[Fraction(float(v)) for v in row] for row in X]
+    for i in range(n):
+        for j in range(n):
+            exact = Fraction(int(i == j)) - sum(Fa[i][k] * Fx[k][j] for k in range(n))
+            assert abs(Fraction(float(R[i, j])) - exact) <= abs(exact) * Fraction(2, 2 ** 52), (i, j)
+
+
+def test_inverse_truth_exact_and_against_long_double():
+    """On A = H D H^T (H Sylvester-Hadamard, D powers of two spanning 2^20)
+    A^-1 = H D^-1 H^T / n^2 is exact in FP64, and the Newton steps with the
+    exact residual reach it from the FP64 oracle's inverse (error 1e-11).  On
+    a U diag(s) V^T matrix they agree with the long-double elimination far
+    below the FP64 oracle's own error."""
+    n = 256
+    H = inputs.sylvester_hadamard(n)
+    e = inputs.rng_for(0, 1410).integers(0, 21, n)
+    e[0], e[1] = 0, 20
+    A = (H * np.ldexp(1.0, e)) @ H.T
+    Ainv = (H * np.ldexp(1.0, -e)) @ H.T / float(n * n)
+    Xo, _, _, _ = oracle.gj_invert_f64(A)
+    assert np.linalg.norm(Xo - Ainv) > 1e-13 * np.linalg.norm(Ainv)
+    T = oracle.inverse_truth(A, Xo)
+    assert np.linalg.norm(T - Ainv) <= 2 * U64 * np.linalg.norm(Ainv)
+    A = inputs.conditioned(150, 1e6, inputs.rng_for(0, 1420))
+    Xo, _, _, _ = oracle.gj_invert_f64(A)
+    Xt, _, _, _ = oracle.gj_invert_f80(A)
+    T = oracle.inverse_truth(A, Xo)
+    err_o = np.linalg.norm(Xo - Xt) / np.linalg.norm(Xt)
+    assert np.linalg.norm(T - Xt) / np.linalg.norm(Xt) <= max(1e-3 * err_o, 1e-14)
+
+
 def test_pivots_to_permutations():
     A = inputs.rng_for(0, 1300).standard_normal((12, 12))
     X, ipiv, jpiv, _ = oracle.gj_invert_f64(A)
