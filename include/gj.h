@@ -36,8 +36,10 @@
  *   multiplication, so it neither overflows nor underflows.
  * Errors.  No C++ exception crosses this boundary.  A singular matrix is not an
  *   error: the call returns GJ_OK and the matrix's gj_result says SINGULAR.
- * Threads.  Library state is read-only after load, so calls on different
- *   streams with different workspaces may run concurrently.
+ * Threads.  Library state is read-only after load, apart from a mutex-guarded
+ *   record of the batched plans uploaded into each workspace (for
+ *   GJ_FLAG_REUSE_PLAN); calls on different streams with different
+ *   workspaces may run concurrently.
  */
 #ifndef GJ_H
 #define GJ_H
@@ -77,9 +79,14 @@ enum {
 /* gj_opts.flags */
 enum {
     GJ_FLAG_REUSE_PLAN = 1,   /* gj_invert_batched: the workspace already holds the plan that
-                                 an earlier call with the same n_host / off_host / piv_off_host
-                                 and workspace uploaded; skip the upload (and the stream
-                                 synchronisation it needs), e.g. while capturing a HIP graph */
+                                 an earlier call uploaded; skip the upload (and the stream
+                                 synchronisation it needs), e.g. while capturing a HIP graph.
+                                 The uploaded tables hold the buffers' addresses, so the call
+                                 must repeat that upload's n_host / off_host / piv_off_host,
+                                 A, X, ipiv, jpiv, res, precision, workspace and ws_bytes;
+                                 otherwise it returns GJ_E_INVALID_ARG and launches nothing
+                                 (the library keeps a signature of the last upload into each
+                                 of the 64 most recently used workspaces) */
     GJ_FLAG_PIVOT_PARTIAL = 2, /* gj_invert, gj_det, gj_solve (FP64): partial pivoting on |a|
                                  instead of the full search of Obs. 2-3: at step k the largest
                                  |a| in column k, first row wins; rows swapped, columns never
@@ -175,8 +182,11 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
  *   ws             workspace of gj_workspace_size(GJ_OP_INVERT_BATCHED, batch,
  *                  n_host, opts) bytes
  * The host arrays are read during the call only.  Matrices up to the on-chip
- * limit are inverted one per workgroup (or one per wavefront) in a single
- * persistent launch; larger ones go through the streaming path.
+ * limit are inverted one per workgroup (or one per wavefront) by persistent
+ * launches that take them from atomic queues, largest first; larger ones go
+ * through the streaming path, one launch per elimination step for all of
+ * them together.  Matrices A and X are checked for overlap with each other
+ * and with the workspace over the span the members cover.
  * Paper: as gj_invert, applied to each matrix.
  */
 gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t *off_host,

@@ -6,8 +6,12 @@ the library's HIP kernels.  PyTorch supplies device memory and the stream.
 If the library is missing, every call raises: there is no CPU fallback.
 
 Entry points (same names as the C ABI):
-    gj_invert, gj_invert_batched, gj_det, gj_workspace_size, gj_status_string,
-    gj_onchip_max_n
+    gj_invert, gj_invert_batched, gj_det, gj_solve,
+    gj_workspace_size, gj_status_string, gj_onchip_max_n, gj_dgemm
+
+Every caller-supplied buffer is checked here (device, dtype, contiguity and
+extent) before the library is called, so a short buffer raises GJError
+instead of reaching a kernel.
 """
 from __future__ import annotations
 
@@ -94,8 +98,8 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-EXPORTS = ("gj_invert", "gj_invert_batched", "gj_det", "gj_solve", "gj_workspace_size",
-           "gj_status_string", "gj_onchip_max_n", "gj_dgemm")
+EXPORTS = ("gj_invert", "gj_invert_batched", "gj_det", "gj_solve",
+           "gj_workspace_size", "gj_status_string", "gj_onchip_max_n", "gj_dgemm")
 
 
 def make_opts(precision=GJ_PREC_FP64, want_resid=False, max_refine_iters=10, flags=0,
@@ -151,6 +155,42 @@ def _workspace(nbytes: int, device):
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
+def _on(t, name, device):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise GJError(f"{name} must be a torch tensor")
+    if not t.is_cuda or t.device != device:
+        raise GJError(f"{name} must be on {device}")
+
+
+def _check_matrix(t, name, rows, cols, device):
+    """A row-major float64 matrix of at least rows x cols on ``device``."""
+    import torch
+    _on(t, name, device)
+    if t.dtype != torch.float64 or t.dim() != 2:
+        raise GJError(f"{name} must be a 2-D float64 tensor")
+    if t.shape[0] < rows or t.shape[1] < cols or t.stride(1) != 1 or t.stride(0) < cols:
+        raise GJError(f"{name} must be row-major with at least {rows} x {cols} elements")
+
+
+def _check_vec(t, name, dtype, count, device):
+    """A contiguous tensor of ``dtype`` holding at least ``count`` elements."""
+    _on(t, name, device)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise GJError(f"{name} must be a contiguous {dtype} tensor")
+    if t.numel() < count:
+        raise GJError(f"{name} holds {t.numel()} elements; {count} are needed")
+
+
+def _check_bytes(t, name, nbytes, device):
+    """A contiguous tensor of at least ``nbytes`` bytes."""
+    _on(t, name, device)
+    if not t.is_contiguous():
+        raise GJError(f"{name} must be contiguous")
+    if t.numel() * t.element_size() < nbytes:
+        raise GJError(f"{name} holds {t.numel() * t.element_size()} bytes; {nbytes} are needed")
+
+
 def _res_tensor(count: int, device):
     import torch
     return torch.empty(count * RESULT_BYTES, dtype=torch.uint8, device=device)
@@ -170,26 +210,45 @@ def gj_invert(A, X=None, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = 
               stream=None):
     """Invert one square FP64 CUDA tensor.  Returns (X, ipiv, jpiv, res) where
     res is the raw device record (use results_to_dicts)."""
-    import torch
     lib = load_library()
-    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.float64 or not A.is_cuda:
-        raise GJError("A must be a square float64 CUDA tensor")
-    if A.stride(1) != 1:
-        raise GJError("A must be row-major (unit column stride)")
+    _check_square(A)
     n = A.shape[0]
     dev = A.device
-    X = torch.empty((n, n), dtype=torch.float64, device=dev) if X is None else X
-    ipiv = torch.empty(n, dtype=torch.int32, device=dev) if ipiv is None else ipiv
-    jpiv = torch.empty(n, dtype=torch.int32, device=dev) if jpiv is None else jpiv
-    res = _res_tensor(1, dev) if res is None else res
+    X, ipiv, jpiv, res = _single_outputs(n, X, ipiv, jpiv, res, dev)
     need = gj_workspace_size(GJ_OP_INVERT, n, None, opts)
+    if need == 0:
+        raise GJError("gj_invert: unsupported size or options")
     if ws is None:
         ws = _workspace(need, dev)
+    _check_bytes(ws, "ws", need, dev)
     st = lib.gj_invert(n, _ptr(A), A.stride(0), _ptr(X), X.stride(0), _ptr(ipiv), _ptr(jpiv),
                        _ptr(res), ctypes.byref(opts) if opts is not None else None, _ptr(ws),
                        ws.numel() * ws.element_size(), _stream_ptr(stream))
     _check(st)
     return X, ipiv, jpiv, res
+
+
+def _single_outputs(n, X, ipiv, jpiv, res, dev):
+    """Allocate the outputs not given; check the ones given."""
+    import torch
+    X = torch.empty((n, n), dtype=torch.float64, device=dev) if X is None else X
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev) if ipiv is None else ipiv
+    jpiv = torch.empty(n, dtype=torch.int32, device=dev) if jpiv is None else jpiv
+    res = _res_tensor(1, dev) if res is None else res
+    _check_matrix(X, "X", n, n, dev)
+    _check_vec(ipiv, "ipiv", torch.int32, n, dev)
+    _check_vec(jpiv, "jpiv", torch.int32, n, dev)
+    _check_bytes(res, "res", RESULT_BYTES, dev)
+    return X, ipiv, jpiv, res
+
+
+def _check_square(A):
+    import torch
+    if (not isinstance(A, torch.Tensor) or A.dim() != 2 or A.shape[0] != A.shape[1]
+            or A.dtype != torch.float64 or not A.is_cuda):
+        raise GJError("A must be a square float64 CUDA tensor")
+    if A.stride(1) != 1 or A.stride(0) < A.shape[1]:
+        raise GJError("A must be row-major (unit column stride)")
 
 
 def gj_dgemm(A, B, C=None, D=None, alpha=1.0, beta=0.0, gamma=0.0, stream=None):
@@ -225,15 +284,22 @@ def gj_solve(A, B, X=None, ipiv=None, jpiv=None, res=None, opts: gj_opts | None 
         raise GJError("A and B must be row-major (unit column stride)")
     n, m = A.shape[0], B.shape[1]
     dev = A.device
+    if B.device != dev:
+        raise GJError(f"B must be on {dev}")
     X = torch.empty((n, m), dtype=torch.float64, device=dev) if X is None else X
     ipiv = torch.empty(n, dtype=torch.int32, device=dev) if ipiv is None else ipiv
     jpiv = torch.empty(n, dtype=torch.int32, device=dev) if jpiv is None else jpiv
     res = _res_tensor(1, dev) if res is None else res
+    _check_matrix(X, "X", n, m, dev)
+    _check_vec(ipiv, "ipiv", torch.int32, n, dev)
+    _check_vec(jpiv, "jpiv", torch.int32, n, dev)
+    _check_bytes(res, "res", RESULT_BYTES, dev)
     need = gj_workspace_size(GJ_OP_SOLVE, n, [m], opts)
     if need == 0:
         raise GJError("gj_solve: unsupported size or options")
     if ws is None:
         ws = _workspace(need, dev)
+    _check_bytes(ws, "ws", need, dev)
     st = lib.gj_solve(n, m, _ptr(A), A.stride(0), _ptr(B), B.stride(0), _ptr(X), X.stride(0),
                       _ptr(ipiv), _ptr(jpiv), _ptr(res),
                       ctypes.byref(opts) if opts is not None else None, _ptr(ws),
@@ -245,16 +311,21 @@ def gj_solve(A, B, X=None, ipiv=None, jpiv=None, res=None, opts: gj_opts | None 
 def gj_det(A, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = None, ws=None, stream=None):
     import torch
     lib = load_library()
-    if A.dim() != 2 or A.shape[0] != A.shape[1] or A.dtype != torch.float64 or not A.is_cuda:
-        raise GJError("A must be a square float64 CUDA tensor")
+    _check_square(A)
     n = A.shape[0]
     dev = A.device
     ipiv = torch.empty(n, dtype=torch.int32, device=dev) if ipiv is None else ipiv
     jpiv = torch.empty(n, dtype=torch.int32, device=dev) if jpiv is None else jpiv
     res = _res_tensor(1, dev) if res is None else res
+    _check_vec(ipiv, "ipiv", torch.int32, n, dev)
+    _check_vec(jpiv, "jpiv", torch.int32, n, dev)
+    _check_bytes(res, "res", RESULT_BYTES, dev)
     need = gj_workspace_size(GJ_OP_DET, n, None, opts)
+    if need == 0:
+        raise GJError("gj_det: unsupported size or options")
     if ws is None:
         ws = _workspace(need, dev)
+    _check_bytes(ws, "ws", need, dev)
     st = lib.gj_det(n, _ptr(A), A.stride(0), _ptr(ipiv), _ptr(jpiv), _ptr(res),
                     ctypes.byref(opts) if opts is not None else None, _ptr(ws),
                     ws.numel() * ws.element_size(), _stream_ptr(stream))
@@ -277,17 +348,30 @@ def gj_invert_batched(sizes, offsets, A, X=None, piv_offsets=None, ipiv=None, jp
         piv_offsets = np.zeros(batch, dtype=np.int64)
         piv_offsets[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
     piv_offsets = np.ascontiguousarray(piv_offsets, dtype=np.int64)
+    if batch < 1 or offsets.shape[0] != batch or piv_offsets.shape[0] != batch:
+        raise GJError("sizes, offsets and piv_offsets must have one entry per member")
+    if (sizes < 1).any() or (offsets < 0).any() or (piv_offsets < 0).any():
+        raise GJError("orders must be >= 1 and offsets >= 0")
+    if not isinstance(A, torch.Tensor) or not A.is_cuda:
+        raise GJError("A must be a CUDA tensor")
     dev = A.device
+    span = int((offsets + sizes.astype(np.int64) ** 2).max())
     total_piv = int((piv_offsets + sizes).max())
     X = torch.empty_like(A) if X is None else X
     ipiv = torch.empty(total_piv, dtype=torch.int32, device=dev) if ipiv is None else ipiv
     jpiv = torch.empty(total_piv, dtype=torch.int32, device=dev) if jpiv is None else jpiv
     res = _res_tensor(batch, dev) if res is None else res
+    _check_vec(A, "A", torch.float64, span, dev)
+    _check_vec(X, "X", torch.float64, span, dev)
+    _check_vec(ipiv, "ipiv", torch.int32, total_piv, dev)
+    _check_vec(jpiv, "jpiv", torch.int32, total_piv, dev)
+    _check_bytes(res, "res", batch * RESULT_BYTES, dev)
     need = gj_workspace_size(GJ_OP_INVERT_BATCHED, batch, sizes, opts)
     if need == 0:
         raise GJError("invalid batch")
     if ws is None:
         ws = _workspace(need, dev)
+    _check_bytes(ws, "ws", need, dev)
     st = lib.gj_invert_batched(batch, sizes.ctypes.data_as(ctypes.c_void_p),
                                offsets.ctypes.data_as(ctypes.c_void_p), _ptr(A), _ptr(X),
                                piv_offsets.ctypes.data_as(ctypes.c_void_p), _ptr(ipiv), _ptr(jpiv),

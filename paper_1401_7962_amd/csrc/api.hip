@@ -625,7 +625,8 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
 // ------------------------------------------------------------ refined path
 constexpr int kDetBlock = 128;          // diagonal blocks of the FP64 determinant
 constexpr double kAcceptResid = 1e-2;   // ||I - A X||_F above this: fall back to FP64
-constexpr double kStall = 0.5;          // an update must at least halve ||R||_F
+constexpr double kStall = 0.5;          // rounding floor: a kept update that neither halves
+                                         // ||R||_F nor comes within 2 ||R||_F^2 ends the loop
 // accurate-residual phase: slices of 19 bits keep every partial sum of the
 // exact products below 2^53 units for n <= 16384; at most 2 updates (from an
 // accepted FP64 iterate with residual R_0 they leave an error of about
@@ -1363,6 +1364,63 @@ gj_status run_resid(int n, const double *A, int64_t lda, const double *X, int64_
 }  // namespace
 }  // namespace gj
 
+// ------------------------------------------------ uploaded batched plans
+// The tables a batched call uploads into the workspace hold the caller's
+// buffer addresses.  A GJ_FLAG_REUSE_PLAN call is therefore accepted only
+// with the workspace, buffers, precision and batch description of the upload
+// it reuses: the library keeps a signature of the last upload into each
+// workspace (at most kPlanSlots workspaces, the oldest forgotten first).
+namespace gj {
+namespace {
+
+constexpr size_t kPlanSlots = 64;
+struct PlanSig { const void *ws; uint64_t sig; };
+std::mutex g_plan_mu;
+std::vector<PlanSig> g_plans;
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t bytes) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < bytes; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+uint64_t plan_signature(int batch, const int32_t *n_host, const int64_t *off_host,
+                        const int64_t *piv_off_host, const void *A, const void *X,
+                        const void *ipiv, const void *jpiv, const void *res, int precision,
+                        size_t ws_bytes) {
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, &batch, sizeof(batch));
+    h = fnv1a(h, n_host, sizeof(int32_t) * (size_t)batch);
+    h = fnv1a(h, off_host, sizeof(int64_t) * (size_t)batch);
+    h = fnv1a(h, piv_off_host, sizeof(int64_t) * (size_t)batch);
+    const void *ptrs[5] = {A, X, ipiv, jpiv, res};
+    h = fnv1a(h, ptrs, sizeof(ptrs));
+    h = fnv1a(h, &precision, sizeof(precision));
+    h = fnv1a(h, &ws_bytes, sizeof(ws_bytes));
+    return h;
+}
+
+void plan_record(const void *ws, uint64_t sig) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    for (PlanSig &p : g_plans)
+        if (p.ws == ws) { p.sig = sig; return; }
+    if (g_plans.size() >= kPlanSlots) g_plans.erase(g_plans.begin());
+    g_plans.push_back(PlanSig{ws, sig});
+}
+
+bool plan_matches(const void *ws, uint64_t sig) {
+    std::lock_guard<std::mutex> lock(g_plan_mu);
+    for (const PlanSig &p : g_plans)
+        if (p.ws == ws) return p.sig == sig;
+    return false;
+}
+
+}  // namespace
+}  // namespace gj
+
 using namespace gj;
 
 extern "C" {
@@ -1540,18 +1598,29 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         if (o.rule != 0) return GJ_E_UNSUPPORTED;   // the batch kernels search the full block
         if (o.flags & (GJ_FLAG_ACCURATE | GJ_FLAG_BLOCKED)) return GJ_E_UNSUPPORTED;   // single matrices only
         if (!ws || ((uintptr_t)ws & 255)) return GJ_E_WORKSPACE;
-        for (int b = 0; b < batch; ++b)
+        size_t mat_end = 0;   // elements of A (and of X) the members span
+        for (int b = 0; b < batch; ++b) {
             if (n_host[b] < 1 || n_host[b] > kMaxN || off_host[b] < 0 || piv_off_host[b] < 0)
                 return GJ_E_INVALID_ARG;
-        if (o.precision == GJ_PREC_FP32_REFINED)
-            return run_refined_batched(batch, n_host, off_host, A, X, piv_off_host, ipiv, jpiv, res,
-                                       o, (char *)ws, ws_bytes, (hipStream_t)stream);
+            mat_end = std::max(mat_end, (size_t)off_host[b] + (size_t)n_host[b] * n_host[b]);
+        }
+        if (overlaps(A, mat_end * 8, X, mat_end * 8) || overlaps(ws, ws_bytes, A, mat_end * 8) ||
+            overlaps(ws, ws_bytes, X, mat_end * 8))
+            return GJ_E_INVALID_ARG;
+        const uint64_t sig = plan_signature(batch, n_host, off_host, piv_off_host, A, X, ipiv,
+                                            jpiv, res, o.precision, ws_bytes);
+        if ((o.flags & GJ_FLAG_REUSE_PLAN) && !plan_matches(ws, sig)) return GJ_E_INVALID_ARG;
+        if (o.precision == GJ_PREC_FP32_REFINED) {
+            const gj_status st = run_refined_batched(batch, n_host, off_host, A, X, piv_off_host,
+                                                     ipiv, jpiv, res, o, (char *)ws, ws_bytes,
+                                                     (hipStream_t)stream);
+            if (st == GJ_OK && !(o.flags & GJ_FLAG_REUSE_PLAN)) plan_record(ws, sig);
+            return st;
+        }
         const bool fp32 = false;
         BatchPlan P;
         if (!plan_batch(batch, n_host, fp32, P)) return GJ_E_INVALID_ARG;
         if (ws_bytes < P.total) return GJ_E_WORKSPACE;
-        for (int b = 0; b < batch; ++b)
-            if (off_host[b] < 0 || piv_off_host[b] < 0) return GJ_E_INVALID_ARG;
         hipStream_t s = (hipStream_t)stream;
         char *w = (char *)ws;
         // device tables
@@ -1593,6 +1662,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
             // the host tables die with this call: wait for the copies
             e = hipStreamSynchronize(s);
             if (e != hipSuccess) return hip_fail(e);
+            plan_record(ws, sig);
         }
         const double eps_default = fp32 ? 0.0 : kEps64;
         if (!P.tasks.empty()) {

@@ -172,6 +172,31 @@ def test_argument_checks_without_gpu(lib):
                                  None) == gj.GJ_E_INVALID_ARG
 
 
+def test_batched_checks_without_gpu(lib):
+    """Checks taken before any HIP call: gj_invert_batched refuses A / X
+    overlapping each other or the workspace, and a reused plan it never
+    uploaded into that workspace."""
+    P = ctypes.c_void_p
+    fake = P(1 << 20)
+    A, X = P(1 << 30), P(1 << 40)
+    n = np.array([4, 5], dtype=np.int32)
+    off = np.array([0, 16], dtype=np.int64)
+    poff = np.array([0, 4], dtype=np.int64)
+    ws = P(1 << 36)
+    # X starts inside A's span (A spans 16 + 25 elements)
+    assert lib.gj_invert_batched(2, n.ctypes.data_as(P), off.ctypes.data_as(P), A,
+                                 P((1 << 30) + 8 * 40), poff.ctypes.data_as(P), fake, fake, fake,
+                                 None, ws, 1 << 20, None) == gj.GJ_E_INVALID_ARG
+    # workspace over X
+    assert lib.gj_invert_batched(2, n.ctypes.data_as(P), off.ctypes.data_as(P), A, X,
+                                 poff.ctypes.data_as(P), fake, fake, fake, None, X, 1 << 20,
+                                 None) == gj.GJ_E_INVALID_ARG
+    reuse = gj.make_opts(flags=gj.GJ_FLAG_REUSE_PLAN)
+    assert lib.gj_invert_batched(2, n.ctypes.data_as(P), off.ctypes.data_as(P), A, X,
+                                 poff.ctypes.data_as(P), fake, fake, fake, ctypes.byref(reuse), ws,
+                                 1 << 20, None) == gj.GJ_E_INVALID_ARG
+
+
 def test_binding_refuses_without_library(tmp_path):
     with pytest.raises(gj.GJError):
         gj._lib_saved = gj._lib
