@@ -38,8 +38,9 @@
  *   error: the call returns GJ_OK and the matrix's gj_result says SINGULAR.
  * Threads.  Library state is read-only after load, apart from a mutex-guarded
  *   record of the batched plans uploaded into each workspace (for
- *   GJ_FLAG_REUSE_PLAN); calls on different streams with different
- *   workspaces may run concurrently.
+ *   GJ_FLAG_REUSE_PLAN) and the per-device address of gj_invert_noalloc's
+ *   array; calls on different streams with different workspaces may run
+ *   concurrently.
  */
 #ifndef GJ_H
 #define GJ_H
@@ -193,6 +194,30 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
                             const double *A, double *X, const int64_t *piv_off_host,
                             int32_t *ipiv, int32_t *jpiv, gj_result *res,
                             const gj_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * gj_invert_noalloc -- gj_invert for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same inversion with the same results, bit for bit, but
+ * with no workspace argument.  Its kernels use a scratch array built into
+ * the library (GJ_NOALLOC_SCRATCH_BYTES bytes, 256-byte aligned), which every
+ * GPU the library runs on holds from module load until the process ends.
+ * The call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine.
+ *   Arguments as for gj_invert, without ws / ws_bytes.  `stream` must belong
+ *   to the calling thread's current device (else GJ_E_INVALID_ARG).
+ *   Returns GJ_E_UNSUPPORTED when the workspace the call needs,
+ *   gj_workspace_size(GJ_OP_INVERT, n, NULL, opts), exceeds
+ *   GJ_NOALLOC_SCRATCH_BYTES (plain FP64: up to n = 2800 or so).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (the kernels initialise what they read).  Calls that overlap in
+ * time on one GPU -- on different streams, or from different threads --
+ * race on the array: serialise them.
+ */
+#define GJ_NOALLOC_SCRATCH_BYTES (64u << 20)
+gj_status gj_invert_noalloc(int32_t n, const double *A, int64_t lda, double *X, int64_t ldx,
+                            int32_t *ipiv, int32_t *jpiv, gj_result *res, const gj_opts *opts,
+                            void *stream);
 
 /*
  * gj_det -- determinant and pivot sequence only.  Runs the same elimination

@@ -6,7 +6,7 @@ the library's HIP kernels.  PyTorch supplies device memory and the stream.
 If the library is missing, every call raises: there is no CPU fallback.
 
 Entry points (same names as the C ABI):
-    gj_invert, gj_invert_batched, gj_det, gj_solve,
+    gj_invert, gj_invert_noalloc, gj_invert_batched, gj_det, gj_solve,
     gj_workspace_size, gj_status_string, gj_onchip_max_n, gj_dgemm
 
 Every caller-supplied buffer is checked here (device, dtype, contiguity and
@@ -79,6 +79,8 @@ def load_library(path: str = LIB_PATH):
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     lib.gj_invert.argtypes = [I32, P, I64, P, I64, P, P, P, P, P, SZ, P]
     lib.gj_invert.restype = I32
+    lib.gj_invert_noalloc.argtypes = [I32, P, I64, P, I64, P, P, P, P, P]
+    lib.gj_invert_noalloc.restype = I32
     lib.gj_invert_batched.argtypes = [I32, P, P, P, P, P, P, P, P, P, P, SZ, P]
     lib.gj_invert_batched.restype = I32
     lib.gj_det.argtypes = [I32, P, I64, P, P, P, P, P, SZ, P]
@@ -98,8 +100,11 @@ def load_library(path: str = LIB_PATH):
     return lib
 
 
-EXPORTS = ("gj_invert", "gj_invert_batched", "gj_det", "gj_solve",
+EXPORTS = ("gj_invert", "gj_invert_noalloc", "gj_invert_batched", "gj_det", "gj_solve",
            "gj_workspace_size", "gj_status_string", "gj_onchip_max_n", "gj_dgemm")
+
+# size of gj_invert_noalloc's built-in scratch array (GJ_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def make_opts(precision=GJ_PREC_FP64, want_resid=False, max_refine_iters=10, flags=0,
@@ -249,6 +254,24 @@ def _check_square(A):
         raise GJError("A must be a square float64 CUDA tensor")
     if A.stride(1) != 1 or A.stride(0) < A.shape[1]:
         raise GJError("A must be row-major (unit column stride)")
+
+
+def gj_invert_noalloc(A, X=None, ipiv=None, jpiv=None, res=None, opts: gj_opts | None = None,
+                      stream=None):
+    """gj_invert with the library's built-in scratch array instead of a
+    workspace (the C entry point allocates nothing; outputs not given are
+    allocated here).  Calls that overlap in time on one GPU race on that
+    array.  Returns (X, ipiv, jpiv, res)."""
+    lib = load_library()
+    _check_square(A)
+    n = A.shape[0]
+    X, ipiv, jpiv, res = _single_outputs(n, X, ipiv, jpiv, res, A.device)
+    st = lib.gj_invert_noalloc(n, _ptr(A), A.stride(0), _ptr(X), X.stride(0), _ptr(ipiv),
+                               _ptr(jpiv), _ptr(res),
+                               ctypes.byref(opts) if opts is not None else None,
+                               _stream_ptr(stream))
+    _check(st)
+    return X, ipiv, jpiv, res
 
 
 def gj_dgemm(A, B, C=None, D=None, alpha=1.0, beta=0.0, gamma=0.0, stream=None):

@@ -1421,6 +1421,39 @@ bool plan_matches(const void *ws, uint64_t sig) {
 }  // namespace
 }  // namespace gj
 
+// ------------------------------------------------------- built-in scratch
+// The workspace of gj_invert_noalloc: one array in the code object, which
+// every GPU the library runs on holds from module load until the process ends
+// (each at its own device address).  In host code the name is only a stand-in
+// for the symbol: the device address comes from hipGetSymbolAddress, once per
+// device, with that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[GJ_NOALLOC_SCRATCH_BYTES];
+
+namespace gj {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the calling thread's current device's array.
+hipError_t scratch_address(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+}  // namespace gj
+
 using namespace gj;
 
 extern "C" {
@@ -1531,6 +1564,35 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
         else if (n > kOnchipMax || o.rule != 0)
             off = a256(big_bufs(big_shape(n, false, big_threads(n, false)), false, 0).end);
         return run_resid(n, A, lda, X, ldx, res, (char *)ws + off, s);
+    } catch (...) {
+        return GJ_E_HIP;
+    }
+}
+
+gj_status gj_invert_noalloc(int32_t n, const double *A, int64_t lda, double *X, int64_t ldx,
+                            int32_t *ipiv, int32_t *jpiv, gj_result *res, const gj_opts *opts,
+                            void *stream) {
+    try {
+        Opts o;
+        if (!read_opts(opts, o)) return GJ_E_INVALID_ARG;
+        if (n < 1 || n > kMaxN) return n < 1 ? GJ_E_INVALID_ARG : GJ_E_UNSUPPORTED;
+        if (o.rule != 0 && o.precision != GJ_PREC_FP64) return GJ_E_UNSUPPORTED;
+        // the whole workspace the call would need must fit the built-in array
+        if (single_ws(n, o, false) > (size_t)GJ_NOALLOC_SCRATCH_BYTES) return GJ_E_UNSUPPORTED;
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e);
+        if (stream) {   // the array used is the stream's device's
+            hipDevice_t sdev = 0;
+            e = hipStreamGetDevice((hipStream_t)stream, &sdev);
+            if (e != hipSuccess) return hip_fail(e);
+            if ((int)sdev != dev) return GJ_E_INVALID_ARG;
+        }
+        void *ws = nullptr;
+        e = scratch_address(dev, &ws);
+        if (e != hipSuccess) return hip_fail(e);
+        return gj_invert(n, A, lda, X, ldx, ipiv, jpiv, res, opts, ws,
+                         (size_t)GJ_NOALLOC_SCRATCH_BYTES, stream);
     } catch (...) {
         return GJ_E_HIP;
     }

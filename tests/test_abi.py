@@ -172,13 +172,22 @@ def test_argument_checks_without_gpu(lib):
                                  None) == gj.GJ_E_INVALID_ARG
 
 
-def test_batched_checks_without_gpu(lib):
-    """Checks taken before any HIP call: gj_invert_batched refuses A / X
+def test_noalloc_and_batched_checks_without_gpu(lib):
+    """Checks taken before any HIP call: gj_invert_noalloc refuses orders whose
+    workspace exceeds its built-in array, and gj_invert_batched refuses A / X
     overlapping each other or the workspace, and a reused plan it never
     uploaded into that workspace."""
     P = ctypes.c_void_p
     fake = P(1 << 20)
     A, X = P(1 << 30), P(1 << 40)
+    lib.gj_invert_noalloc.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P, ctypes.c_int64, P, P,
+                                      P, P, P]
+    assert lib.gj_invert_noalloc(0, A, 1, X, 1, fake, fake, fake, None, None) == gj.GJ_E_INVALID_ARG
+    assert lib.gj_invert_noalloc(4096, A, 4096, X, 4096, fake, fake, fake, None,
+                                 None) == gj.GJ_E_UNSUPPORTED
+    assert lib.gj_invert_noalloc(20000, A, 20000, X, 20000, fake, fake, fake, None,
+                                 None) == gj.GJ_E_UNSUPPORTED
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 2500) <= gj.NOALLOC_SCRATCH_BYTES
     n = np.array([4, 5], dtype=np.int32)
     off = np.array([0, 16], dtype=np.int64)
     poff = np.array([0, 4], dtype=np.int64)
