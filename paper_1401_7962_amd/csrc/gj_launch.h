@@ -10,9 +10,11 @@ hipError_t launch_zero_u32(uint32_t *p, int count, hipStream_t s);
 // integer environment override (dflt when unset or unparsable)
 int env_int(const char *name, int dflt);
 
-// on-chip task classes for batches: 0 = (kind 0, E 8, n in 65..128),
-// 1..4 = (kind 1, E 8/4/2/1, n in 33..64 / 17..32 / 9..16 / 1..8)
-constexpr int kOnchipClasses = 5;
+// on-chip task classes: c = 0..7 is kind 0 (one matrix per workgroup) with
+// E = 8 - c register blocks per thread and dimension (n <= 16 E); c = 8..15
+// is kind 1 (one matrix per wavefront) with E = 16 - c (n <= 8 E).
+// onchip_class_of returns a class index in [0, kOnchipClasses), or -1.
+constexpr int kOnchipClasses = 16;
 int onchip_class_of(int n, bool single);
 int onchip_class_kind(int c);
 hipError_t launch_onchip_class(bool fp32, int cls, const MatDesc *mats, const OnchipTask *tasks,

@@ -1,9 +1,11 @@
 // onchip.hip -- full-pivot Gauss-Jordan with the matrix held in registers.
 //
-// One matrix per 256-thread workgroup (kind 0, n <= 128) or per wavefront
-// (kind 1, n <= 64).  The n x n array (the in-place [A|D] of eqs. 3-10) is
-// distributed cyclically over a TR x TC thread grid: thread (tr, tc) holds
-// rows a*TR + tr and columns b*TC + tc, EA x EB values in VGPRs.
+// One matrix per 256-thread workgroup (kind 0, a 16 x 16 thread grid) or per
+// wavefront (kind 1, an 8 x 8 lane grid).  The n x n array (the in-place
+// [A|D] of eqs. 3-10) is distributed cyclically: thread (tr, tc) holds rows
+// a*TR + tr and columns b*TC + tc, E x E values in VGPRs, with E the smallest
+// register block that covers n (n <= TR E), so padding costs at most
+// (1 + 1/E)^2 of the real work.
 //
 // One step k (paper section 2):
 //   1. the winner of the pivot search (Obs. 2-3) is already known from the
@@ -19,11 +21,11 @@
 //   5. while the new values are in registers, each thread scans its part of
 //      the next trailing block in row-major order (so strict '>' keeps the
 //      first maximum), and the workgroup reduces (|a|, row<<16|col).
-// The determinant (eq. 13) is accumulated as an exact mantissa/exponent pair.
-// The final depivoting (Obs. 3) is folded into the store: element (i, j) of
-// the working array goes to X(g[i], h[j]), where g and h are the inverse
-// permutations of the reversed swap sequence, built forward one swap per
-// step.
+// The determinant (eq. 13) is multiplied up in step order as an exact
+// mantissa/exponent pair.  The final depivoting (Obs. 3) is folded into the
+// store: element (i, j) of the working array goes to X(g[i], h[j]), where g
+// (h) follows row i (column j) through the column (row) swaps of the result
+// in reverse step order; one thread traces each index at the end.
 #include <algorithm>
 
 #include "gj_launch.h"
@@ -162,8 +164,6 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
         L.pcol[x] = (T)0;
         L.newr[x] = (T)0;
         L.newc[x] = (T)0;
-        L.g[x] = x;
-        L.h[x] = x;
     }
 
     // Non-finite candidates: every candidate of step 0 is checked here.  After
@@ -194,17 +194,23 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
         const int ar = r / TR, trr = r % TR, ak = k / TR, trk = k % TR;
         const int bc = cc / TC, tcc = cc % TC, bk = k / TC, tck = k % TC;
 
-        // stage the four swapped lines and the scaled pivot row (eq. 14).
+        // Stage the four swapped lines and the scaled pivot row (eq. 14).
+        // Each line is written in its natural order and then the one or two
+        // entries that the swap moves are written again.  A line written by
+        // lanes of one wavefront only (the rows) relies on its writes landing
+        // in program order; for the columns, written by lanes of every
+        // wavefront, the natural write of a moved position is left out.
         // Row r: its owners extract it (uniform branches on ar), take the
         // signed pivot from the lane that holds column c, and divide.
         if (tr == trr) {
 #pragma unroll
             for (int a = 0; a < EA; ++a)
                 if (a == ar) {
-                    T xc = (T)0;
+                    T xc = (T)0, xk = (T)0;
 #pragma unroll
-                    for (int b = 0; b < EB; ++b)
+                    for (int b = 0; b < EB; ++b) {
                         if (b == bc) xc = v[a][b];
+                    }
                     // the pivot sits in lane (trr, tcc) of this row group
                     const int src = (trr * TC + tcc) & (kWave - 1);
                     T p;
@@ -215,76 +221,82 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
                     } else {
                         p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xc), src));
                     }
-                    if (tc == tcc) L.pv = p;
                     const T y = M::one() / p;   // RN(1/p): the pivot slot, and the division seed
                     const bool p_ok = div_pivot_ok(p);
                     bool slow = false;
+                    T q[EB];
 #pragma unroll
-                    for (int b = 0; b < EB; ++b) {
-                        const int jo = b * TC + tc;
-                        const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
-                        const T qv = div_pivot_fast(v[a][b], p, y, p_ok, slow);
-                        L.prow[jn] = (jo == cc) ? y : qv;
-                    }
+                    for (int b = 0; b < EB; ++b) q[b] = div_pivot_fast(v[a][b], p, y, p_ok, slow);
                     if (slow) {   // operands outside the corrected-quotient range
 #pragma unroll
-                        for (int b = 0; b < EB; ++b) {
-                            const int jo = b * TC + tc;
-                            const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
-                            if (jo != cc) L.prow[jn] = div_pivot(v[a][b], p, y, p_ok);
-                        }
+                        for (int b = 0; b < EB; ++b) q[b] = div_pivot(v[a][b], p, y, p_ok);
+                    }
+#pragma unroll
+                    for (int b = 0; b < EB; ++b) {
+                        L.prow[b * TC + tc] = q[b];
+                        if (b == bk) xk = q[b];
+                    }
+                    // the column swap: column k's quotient goes to c, 1/p to k
+                    if (tc == tck) L.prow[cc] = xk;
+                    if (tc == tcc) {
+                        L.prow[k] = y;
+                        L.pv = p;
                     }
                 }
         }
-        if (tr == trk) {
+        if (tr == trk) {                       // old row k -> row r, columns swapped
 #pragma unroll
             for (int a = 0; a < EA; ++a)
                 if (a == ak) {
+                    T xk = (T)0, xc = (T)0;
 #pragma unroll
                     for (int b = 0; b < EB; ++b) {
-                        const int jo = b * TC + tc;
-                        const int jn = (jo == cc) ? k : ((jo == k) ? cc : jo);
-                        L.newr[jn] = v[a][b];
+                        L.newr[b * TC + tc] = v[a][b];
+                        if (b == bk) xk = v[a][b];
+                        if (b == bc) xc = v[a][b];
                     }
+                    if (tc == tck) L.newr[cc] = xk;
+                    if (tc == tcc) L.newr[k] = xc;
                 }
         }
-        if (tc == tcc) {
+        if (tc == tcc) {                       // the multipliers, rows swapped
 #pragma unroll
             for (int b = 0; b < EB; ++b)
                 if (b == bc) {
+                    T vk = (T)0;
 #pragma unroll
                     for (int a = 0; a < EA; ++a) {
-                        const int io = a * TR + tr;
-                        const int in = (io == r) ? k : ((io == k) ? r : io);
-                        L.pcol[in] = v[a][b];
+                        if (a != ar || tr != trr) L.pcol[a * TR + tr] = v[a][b];
+                        if (a == ak) vk = v[a][b];
                     }
+                    if (tr == trk) L.pcol[r] = vk;
                 }
         }
-        if (tc == tck) {
+        if (tc == tck) {                       // old column k -> column c, rows swapped
 #pragma unroll
             for (int b = 0; b < EB; ++b)
                 if (b == bk) {
+                    T vk = (T)0, vr = (T)0;
 #pragma unroll
                     for (int a = 0; a < EA; ++a) {
-                        const int io = a * TR + tr;
-                        const int in = (io == r) ? k : ((io == k) ? r : io);
-                        L.newc[in] = v[a][b];
+                        if ((a != ar || tr != trr) && (a != ak || tr != trk)) L.newc[a * TR + tr] = v[a][b];
+                        if (a == ak) vk = v[a][b];
+                        if (a == ar) vr = v[a][b];
                     }
+                    if (tr == trk) L.newc[r] = vk;
+                    if (tr == trr) L.newc[k] = vr;
                 }
         }
-        group_sync<NW>();
-
-        // bookkeeping off the critical path: pivots, depivoting maps and the
-        // determinant (eq. 13)
         if (t == 0) {
             L.ip[k] = r;
             L.jp[k] = cc;
-            int tmp = L.g[k]; L.g[k] = L.g[cc]; L.g[cc] = tmp;
-            tmp = L.h[k]; L.h[k] = L.h[r]; L.h[r] = tmp;
-            det.mul(L.pv);
-            if (r != k) det.sign = -det.sign;
-            if (cc != k) det.sign = -det.sign;
         }
+        group_sync<NW>();
+
+        // eq. 13, in step order (every lane keeps the same product)
+        det.mul(L.pv);
+        if (r != k) det.sign = -det.sign;
+        if (cc != k) det.sign = -det.sign;
 
         // install the swapped row r and column c; clear column k (it becomes
         // fma(-q, 1/p, 0) below, the D column of eq. 15)
@@ -337,7 +349,23 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
         }
     }
 
-    // ensure thread 0's last swaps of g/h and pivots are visible
+    // Depivoting maps: g (h) follows working row i (column j) through the
+    // column (row) swaps of the result, undone in reverse step order; one
+    // thread per index.
+    group_sync<NW>();
+    for (int x = t; x < 2 * N; x += TR * TC) {
+        const bool row = x < N;
+        const int i0 = row ? x : x - N;
+        int pos = i0;
+        if (code == GJ_RES_OK && i0 < n) {
+            const int32_t *sw = row ? L.jp : L.ip;
+            for (int kk = n - 1; kk >= 0; --kk) {
+                const int s2 = sw[kk];
+                pos = (pos == kk) ? s2 : ((pos == s2) ? kk : pos);
+            }
+        }
+        if (row) L.g[i0] = pos; else L.h[i0] = pos;
+    }
     group_sync<NW>();
     for (int x = t; x < n; x += TR * TC) {
         ipiv[x] = (x < rank) ? L.ip[x] : -1;
@@ -439,18 +467,18 @@ hipError_t launch_zero_u32(uint32_t *p, int count, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Task classes: (kind, E).  Class c covers n in (lo, hi].
-struct OnchipClass { int kind, e, lo, hi; };
-static const OnchipClass kClasses[kOnchipClasses] = {
-    {0, 8, 64, 128}, {1, 8, 32, 64}, {1, 4, 16, 32}, {1, 2, 8, 16}, {1, 1, 0, 8}};
-
+// Task classes: c = 0..7 is kind 0 with E = 8 - c (one matrix per workgroup,
+// n <= 16 E), c = 8..15 is kind 1 with E = 16 - c (one matrix per
+// wavefront, n <= 8 E).  A batch sends n > 64 to kind 0 and n <= 64 to kind
+// 1, each with the smallest E that covers n, so the padded work stays below
+// (1 + 1/E)^2 of the real work; classes run largest E first.  A single
+// matrix always uses kind 0 (all four wavefronts).
 int onchip_class_of(int n, bool single) {
-    if (single) return n <= 32 ? 7 : (n <= 64 ? 6 : 0);   // single matrices: all four wavefronts
-    for (int c = 0; c < kOnchipClasses; ++c)
-        if (n > kClasses[c].lo && n <= kClasses[c].hi) return c;
-    return -1;
+    if (n < 1 || n > 128) return -1;
+    if (single || n > 64) return 8 - (n + 15) / 16;
+    return 16 - (n + 7) / 8;
 }
-int onchip_class_kind(int c) { return c < kOnchipClasses ? kClasses[c].kind : 0; }
+int onchip_class_kind(int c) { return c < 8 ? 0 : 1; }
 
 template <typename T, int KIND, int E>
 static hipError_t launch_cls(const MatDesc *mats, const OnchipTask *tasks, int ntasks,
@@ -474,30 +502,35 @@ static hipError_t launch_cls(const MatDesc *mats, const OnchipTask *tasks, int n
     return hipGetLastError();
 }
 
-// cls: 0..4 batched classes (kClasses), 6 / 7: single matrix with E = 4 / 2.
+template <typename T>
+static hipError_t launch_cls_t(int cls, const MatDesc *mats, const OnchipTask *tasks, int ntasks,
+                               uint32_t *queue, const MatDesc &single, const double *A, double *X,
+                               int32_t *ipiv, int32_t *jpiv, gj_result *res, double zero_tol,
+                               double eps_default, int det_only, const int32_t *run_flag,
+                               hipStream_t s) {
+#define GJ_CLS(C, K, EE)                                                                        \
+    case C:                                                                                     \
+        return launch_cls<T, K, EE>(mats, tasks, ntasks, queue, single, 1, A, X, ipiv, jpiv,    \
+                                    res, zero_tol, eps_default, det_only, run_flag, s)
+    switch (cls) {
+        GJ_CLS(0, 0, 8); GJ_CLS(1, 0, 7); GJ_CLS(2, 0, 6); GJ_CLS(3, 0, 5);
+        GJ_CLS(4, 0, 4); GJ_CLS(5, 0, 3); GJ_CLS(6, 0, 2); GJ_CLS(7, 0, 1);
+        GJ_CLS(8, 1, 8); GJ_CLS(9, 1, 7); GJ_CLS(10, 1, 6); GJ_CLS(11, 1, 5);
+        GJ_CLS(12, 1, 4); GJ_CLS(13, 1, 3); GJ_CLS(14, 1, 2); GJ_CLS(15, 1, 1);
+    }
+#undef GJ_CLS
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_onchip_class(bool fp32, int cls, const MatDesc *mats, const OnchipTask *tasks,
                                int ntasks, uint32_t *queue, const MatDesc &single, const double *A,
                                double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,
                                double zero_tol, double eps_default, int det_only,
                                const int32_t *run_flag, hipStream_t s) {
-#define GJ_CLS(K, EE)                                                                         \
-    return fp32 ? launch_cls<float, K, EE>(mats, tasks, ntasks, queue, single, 1, A, X, ipiv,  \
-                                           jpiv, res, zero_tol, eps_default, det_only,         \
-                                           run_flag, s)                                        \
-                : launch_cls<double, K, EE>(mats, tasks, ntasks, queue, single, 1, A, X, ipiv, \
-                                            jpiv, res, zero_tol, eps_default, det_only,        \
-                                            run_flag, s)
-    switch (cls) {
-        case 0: GJ_CLS(0, 8);
-        case 1: GJ_CLS(1, 8);
-        case 2: GJ_CLS(1, 4);
-        case 3: GJ_CLS(1, 2);
-        case 4: GJ_CLS(1, 1);
-        case 6: GJ_CLS(0, 4);
-        case 7: GJ_CLS(0, 2);
-    }
-#undef GJ_CLS
-    return hipErrorInvalidValue;
+    return fp32 ? launch_cls_t<float>(cls, mats, tasks, ntasks, queue, single, A, X, ipiv, jpiv,
+                                      res, zero_tol, eps_default, det_only, run_flag, s)
+                : launch_cls_t<double>(cls, mats, tasks, ntasks, queue, single, A, X, ipiv, jpiv,
+                                       res, zero_tol, eps_default, det_only, run_flag, s);
 }
 
 // Single matrix (n <= 128) on one workgroup.

@@ -206,6 +206,20 @@ def test_noalloc_and_batched_checks_without_gpu(lib):
                                  1 << 20, None) == gj.GJ_E_INVALID_ARG
 
 
+def test_batch_plans_every_order(lib):
+    """The host-side batch plans (plain and refined) over every order up to
+    300, each on-chip task class included: they build without error and the
+    workspace grows with the batch."""
+    sizes = np.arange(1, 301, dtype=np.int32)
+    for prec in (gj.GJ_PREC_FP64, gj.GJ_PREC_FP32_REFINED):
+        o = gj.make_opts(precision=prec)
+        full = gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, len(sizes), sizes, o)
+        small = gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 128, sizes[:128], o)
+        assert 0 < small < full
+        for n in range(1, 129):
+            assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 3, np.full(3, n, np.int32), o) > 0
+
+
 def test_binding_refuses_without_library(tmp_path):
     with pytest.raises(gj.GJError):
         gj._lib_saved = gj._lib

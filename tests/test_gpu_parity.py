@@ -242,3 +242,69 @@ def test_batched_mixed(gj):
         _assert_same(Ab, got, oracle.gj_invert_f64(Ab), f"member {b} n={n}")
         n_sing += rs[b]["code"] == 1
     assert n_sing >= len(singular) - 2   # tiny members (n < 3) cannot host the planted sum
+
+
+def _batched_vs_oracle(gj, mats, where):
+    import torch
+    sizes = np.array([M.shape[0] for M in mats], dtype=np.int32)
+    offs = np.zeros(len(sizes), dtype=np.int64)
+    offs[1:] = np.cumsum(sizes.astype(np.int64) ** 2)[:-1]
+    packed = np.concatenate([M.ravel() for M in mats])
+    A = torch.from_numpy(packed).to("cuda")
+    X, ipiv, jpiv, res, poff = gj.gj_invert_batched(sizes, offs, A)
+    torch.cuda.synchronize()
+    Xh, ih, jh = X.cpu().numpy(), ipiv.cpu().numpy(), jpiv.cpu().numpy()
+    rs = gj.results_to_dicts(res)
+    for b, M in enumerate(mats):
+        n = M.shape[0]
+        got = (Xh[offs[b]:offs[b] + n * n].reshape(n, n), ih[poff[b]:poff[b] + n],
+               jh[poff[b]:poff[b] + n], rs[b])
+        _assert_same(M, got, oracle.gj_invert_f64(M), f"{where} member {b} n={n}")
+    return rs
+
+
+BOUNDARY_ORDERS = [1, 2, 7, 8, 9, 15, 16, 17, 24, 25, 32, 33, 40, 41, 48, 49, 56, 57, 63, 64,
+                   65, 79, 80, 81, 96, 97, 111, 112, 113, 127, 128]
+
+
+def test_batched_every_onchip_class(gj):
+    """Every on-chip task class (one matrix per wavefront for n <= 64, per
+    workgroup above, register blocks of 1..8 per thread and dimension) at
+    both ends of its range, three members each, interleaved."""
+    rng = inputs.rng_for(0, 8800)
+    mats = [rng.standard_normal((n, n)) for n in BOUNDARY_ORDERS for _ in range(3)]
+    rng.shuffle(mats)
+    _batched_vs_oracle(gj, mats, "classes")
+
+
+def test_batched_onchip_ties_and_singular(gj):
+    """Hadamard members (a tie at every step, exact arithmetic), exactly
+    singular ones, a zero matrix, and scaled copies with ties across
+    wavefronts, in one batch."""
+    mats = []
+    for n in (4, 8, 16, 32, 64, 128):
+        H = inputs.sylvester_hadamard(n)
+        mats.append(H)
+        S = H.copy()
+        S[:, n - 1] = S[:, 0] + S[:, 1]
+        if n >= 4:
+            mats.append(S)
+        mats.append(np.kron(np.eye(2), inputs.sylvester_hadamard(n // 2)) if n >= 2 else H)
+    mats.append(np.zeros((20, 20)))
+    mats.append(np.ones((70, 70)))
+    rs = _batched_vs_oracle(gj, mats, "ties")
+    assert sum(r["code"] == 1 for r in rs) >= 8
+
+
+@pytest.mark.parametrize("n", [1, 5, 16, 17, 33, 64, 65, 100, 128])
+def test_det_only_onchip(gj, n):
+    """gj_det on the on-chip path: the pivots and determinant of gj_invert."""
+    import torch
+    A = inputs.single_normal(n, offset=900 + n)
+    ipiv, jpiv, res = gj.gj_det(_dev(A))
+    torch.cuda.synchronize()
+    _, io, jo, ro = oracle.gj_invert_f64(A)
+    r = gj.results_to_dicts(res)[0]
+    assert np.array_equal(ipiv.cpu().numpy(), io) and np.array_equal(jpiv.cpu().numpy(), jo)
+    assert r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"]
+    assert r["det_sign"] == ro["det_sign"]
