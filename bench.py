@@ -58,6 +58,46 @@ def _traffic_per_launch(kernel_key: str):
         return None
 
 
+def host_info() -> dict:
+    """CPU model and the cores this process may use (the oracle legs use all
+    of them unless OMP_NUM_THREADS caps it)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    import oracle
+    return {"cpu_model": model, "cores_available": len(os.sched_getaffinity(0)),
+            "oracle_threads": oracle.host_threads()}
+
+
+def _oracle_sample_rate(A, all_steps: int, one_steps: int):
+    """Inversions/s of the FP64 oracle on a square matrix, from the first
+    steps of the run (every step does the same n(n-1) updates; the shrinking
+    search makes the scaled time a slight overestimate): all host cores
+    (OpenMP form, bitwise the serial oracle) and one core (serial oracle)."""
+    import oracle
+    n = A.shape[0]
+    threads = oracle.host_threads()
+    t0 = time.perf_counter()
+    oracle.gj_invert_f64_par(A, threads, max_steps=min(all_steps, n))
+    t_all = (time.perf_counter() - t0) * n / min(all_steps, n)
+    t0 = time.perf_counter()
+    oracle.gj_first_steps(A, min(one_steps, n))
+    t_one = (time.perf_counter() - t0) * n / min(one_steps, n)
+    return {"all_cores_s_per_inversion": t_all, "threads": threads,
+            "one_core_s_per_inversion": t_one,
+            "sample": f"first {min(all_steps, n)} (all cores) and {min(one_steps, n)} (one core) "
+                      f"of {n} steps, scaled by n / steps"}
+
+
+def _rel(a, b) -> float:
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
 def bench_headline(steps: int, warmup: int, n: int = 4096):
     import torch
     import paper_1401_7962_amd as gj
@@ -101,7 +141,33 @@ def bench_headline(steps: int, warmup: int, n: int = 4096):
     alg_bytes = 16.0 * n * n
     achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
     traffic = _traffic_per_launch(f"gj_big_step_f64_n{n}")
+    # the metric's comparison on the same input: FP32 elimination + FP64
+    # Newton-Schulz, against the plain result (which the tests hold bit for
+    # bit to the FP64 oracle at this order)
+    ro = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED)
+    Xr = torch.empty_like(A)
+    ipr = torch.empty_like(ipiv)
+    jpr = torch.empty_like(jpiv)
+    resr = torch.empty_like(res)
+    wsr = torch.empty(gj.gj_workspace_size(gj.GJ_OP_INVERT, n, None, ro), dtype=torch.uint8, device=dev)
+    gj.gj_invert(A, Xr, ipr, jpr, resr, ro, wsr, stream)
+    torch.cuda.synchronize()
+    evr = _events(2 * 3, stream)
+    for k in range(3):
+        evr[2 * k].record()
+        gj.gj_invert(A, Xr, ipr, jpr, resr, ro, wsr, stream)
+        evr[2 * k + 1].record()
+    torch.cuda.synchronize()
+    ref_ms = min(evr[2 * k].elapsed_time(evr[2 * k + 1]) for k in range(3))
+    rr = gj.results_to_dicts(resr)[0]
+    refined = {"ms_per_inv": round(ref_ms, 2), "inversions_per_s": round(1e3 / ref_ms, 4),
+               "code": rr["code"], "refine_iters": rr["refine_iters"],
+               "rel_frobenius_vs_fp64": float(torch.linalg.norm(Xr - X) / torch.linalg.norm(X)),
+               "logabsdet_minus_fp64": rr["logabsdet"] - r["logabsdet"],
+               "speedup_over_fp64": round(ms_per_inv / ref_ms, 3)}
+    del wsr, Xr
     return {
+        "refined": refined,
         "ms_per_inv": ms_per_inv,
         "value": 1e3 / ms_per_inv,
         "step_phase_ms": step_ms,
@@ -153,7 +219,17 @@ def bench_latency_small(reps: int = 200):
         torch.cuda.synchronize()
         us = e0.elapsed_time(e1) * 1e3 / reps
         r = gj.results_to_dicts(res)[0]
-        out[name] = {"n": n, "us_per_inversion": round(us, 2), "code": r["code"], "det": r["det"]}
+        import oracle
+        t0 = time.perf_counter()
+        for _ in range(20):
+            Xo, io, jo, ro = oracle.gj_invert_f64(A_h)
+        ous = (time.perf_counter() - t0) / 20 * 1e6
+        same = (X.cpu().numpy().tobytes() == Xo.tobytes() and np.array_equal(ip.cpu().numpy(), io)
+                and np.array_equal(jp.cpu().numpy(), jo) and r["det_mant"] == ro["det_mant"]
+                and r["det_exp"] == ro["det_exp"])
+        out[name] = {"n": n, "us_per_inversion": round(us, 2), "code": r["code"], "det": r["det"],
+                     "bitwise_equal_to_oracle": bool(same),
+                     "oracle_one_core_us_per_inversion": round(ous, 2)}
     return out
 
 
@@ -218,6 +294,20 @@ def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
         reuse = gj.make_opts(precision=prec, flags=gj.GJ_FLAG_REUSE_PLAN)
         ms = _graph_time(lambda st: gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, reuse,
                                                           ws, st), reps)
+        # the streaming members' step launches, timed eagerly between events:
+        # every launch reads and writes each active member's array once, so
+        # the phase moves 2 esz sum(n^3) bytes (members above the on-chip
+        # limit)
+        ev = _events(2, torch.cuda.current_stream())
+        so = gj.make_opts(precision=prec, flags=gj.GJ_FLAG_REUSE_PLAN,
+                          step_events=(ctypes_ptr(ev[0]), ctypes_ptr(ev[1])))
+        gj.gj_invert_batched(sizes, offs, A, X, poff, ip, jp, res, so, ws)
+        torch.cuda.synchronize()
+        steps_ms = ev[0].elapsed_time(ev[1])
+        esz = 8 if prec == gj.GJ_PREC_FP64 else 4
+        big = sizes[sizes > gj.gj_onchip_max_n()].astype(np.float64)
+        step_bytes = 2.0 * esz * float((big ** 3).sum())
+        gbs = step_bytes / (steps_ms * 1e-3) / 1e9
         del ws
         raw = np.frombuffer(res.cpu().numpy().tobytes(), dtype=np.uint8).reshape(batch, gj.RESULT_BYTES)
         codes = raw[:, 0:4].copy().view(np.int32)[:, 0]
@@ -226,6 +316,12 @@ def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
         cf = sizes * np.log(conds) / 2.0
         rel_det = np.abs(logdet - cf) / np.abs(cf)
         out[name] = {"ms": round(ms, 2), "inversions_per_s": round(batch / (ms * 1e-3), 1),
+                     "streaming_steps_ms": round(steps_ms, 2),
+                     "step_roofline": {"bound": "hbm",
+                                       "kernel": "gj_big_step, batched (%s)" % ("FP64" if esz == 8 else "FP32"),
+                                       "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                       "alg_bytes": step_bytes},
                      "codes": {str(c): int((codes == c).sum()) for c in np.unique(codes)},
                      "mean_refine_iters": float(iters.mean()),
                      "max_rel_logdet_err_vs_closed_form": float(rel_det.max()),
@@ -234,19 +330,81 @@ def bench_batch_conditioned(batch: int = 20_000, reps: int = 2):
     d = torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"])
     out["refined_vs_plain_rel_frobenius_whole_batch"] = float(d)
     out["speedup_refined_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined"]["ms"], 3)
+    out["oracle"] = _batch_conditioned_oracle(sizes, offs, conds, A, Xs)
     return out
 
 
-def bench_batch_uneven(batch: int = 100_000, reps: int = 3):
-    """100,000 FP64 matrices, n uniform in [8,128], 1% rank n-1: one persistent
-    on-chip launch.  Reports inversions/s and FP64 FMA throughput (n^3 FMAs =
-    2 n^3 flop per inversion)."""
+def _batch_conditioned_oracle(sizes, offs, conds, A, Xs, n_sample: int = 200, n_one: int = 24):
+    """A stratified sample of the 20,000 members (sorted by order, then every
+    (batch / n_sample)-th): the FP64 oracle on all host cores (and on one
+    core for fewer of them), both scaled to the whole batch by sum n^3; the
+    GPU's plain and refined inverses of the sample against the oracle's and
+    against reference inverses (Newton steps with an exactly formed
+    residual).  The refined bar (R-16): forward error <= 4 x the oracle's
+    own + 1e-14, and 1e-12 against the oracle for cond <= 1e4."""
+    import oracle
+    batch = len(sizes)
+    order = np.argsort(sizes.astype(np.int64) * 100 + np.log10(conds).astype(np.int64), kind="stable")
+    pick = order[:: max(1, batch // n_sample)][:n_sample]
+    mats = [A[int(offs[b]): int(offs[b]) + int(sizes[b]) ** 2].cpu().numpy() for b in pick]
+    xg = {name: [X[int(offs[b]): int(offs[b]) + int(sizes[b]) ** 2].cpu().numpy() for b in pick]
+          for name, X in Xs.items()}
+    ns = sizes[pick].astype(np.int32)
+    so = np.zeros(len(pick), dtype=np.int64)
+    so[1:] = np.cumsum(ns.astype(np.int64) ** 2)[:-1]
+    packed = np.concatenate(mats)
+    t0 = time.perf_counter()
+    Xo, _, _, _ = oracle.gj_invert_batched(ns, so, packed)
+    t_all = time.perf_counter() - t0
+    one = np.arange(0, len(pick), max(1, len(pick) // n_one))[:n_one]
+    t0 = time.perf_counter()
+    for i in one:
+        oracle.gj_invert_f64(mats[i].reshape(int(ns[i]), int(ns[i])))
+    t_one = time.perf_counter() - t0
+    cube = sizes.astype(np.float64) ** 3
+    scale_all = cube.sum() / (ns.astype(np.float64) ** 3).sum()
+    scale_one = cube.sum() / (ns[one].astype(np.float64) ** 3).sum()
+    worst = {"fp32_refined": 0.0, "plain_fp64": 0.0}
+    max_vs_oracle_low_cond = 0.0
+    max_err = {"fp32_refined": 0.0, "plain_fp64": 0.0, "fp64_oracle": 0.0}
+    for i, b in enumerate(pick):
+        n = int(ns[i])
+        Ab = mats[i].reshape(n, n)
+        Xob = Xo[so[i]: so[i] + n * n].reshape(n, n)
+        T = oracle.inverse_truth(Ab, Xob)
+        err_o = _rel(Xob, T)
+        max_err["fp64_oracle"] = max(max_err["fp64_oracle"], err_o)
+        for name in ("fp32_refined", "plain_fp64"):
+            e = _rel(xg[name][i].reshape(n, n), T)
+            max_err[name] = max(max_err[name], e)
+            worst[name] = max(worst[name], e / (4 * err_o + 1e-14))
+        if conds[b] <= 1e4:
+            max_vs_oracle_low_cond = max(max_vs_oracle_low_cond,
+                                         _rel(xg["fp32_refined"][i].reshape(n, n), Xob))
+    return {"sample_members": int(len(pick)), "threads": oracle.host_threads(),
+            "all_cores_inversions_per_s": round(batch / (t_all * scale_all), 1),
+            "one_core_inversions_per_s": round(batch / (t_one * scale_one), 1),
+            "sample": f"{len(pick)} members stratified by order and condition (all cores); "
+                      f"{len(one)} of them on one core; scaled by sum n^3",
+            "max_forward_error_vs_reference": max_err,
+            "max_error_over_bar": worst,
+            "max_refined_vs_oracle_cond_le_1e4": max_vs_oracle_low_cond}
+
+
+def bench_batch_uneven(batch: int = 100_000, reps: int = 3, oracle_sample: int = 10000,
+                       oracle_sample_one: int = 1000):
+    """100,000 FP64 matrices, n uniform in [8,128], 1% rank n-1: the on-chip
+    persistent launches (one per register-block class).  Reports
+    inversions/s, the FP64 FMA rate against the FP64 vector peak (n^3 FMAs
+    = 2 n^3 flop per inversion), and the FP64 oracle on a sample of the same
+    members (all host cores, and one core), whose results the GPU's must
+    equal bit for bit."""
     import torch
+    import oracle
     import paper_1401_7962_amd as gj
     from paper_1401_7962_amd import inputs
     sizes, offs, packed, singular = inputs.batch_uneven(batch)
     A = torch.from_numpy(packed).cuda()
-    del packed
     X = torch.empty_like(A)
     poff = np.zeros(batch, dtype=np.int64)
     poff[1:] = np.cumsum(sizes.astype(np.int64))[:-1]
@@ -262,15 +420,40 @@ def bench_batch_uneven(batch: int = 100_000, reps: int = 3):
                                                       ws, st), reps)
     codes = np.frombuffer(res.cpu().numpy().tobytes(), dtype=np.int32).reshape(batch, 14)[:, 0]
     flops = 2.0 * float((sizes.astype(np.float64) ** 3).sum())
+    tflops = flops / (ms * 1e-3) / 1e12
+    # the oracle on the first members (a uniform draw of orders): all cores,
+    # then one core on fewer; both scaled to the whole batch by sum n^3
+    cube = sizes.astype(np.float64) ** 3
+    m_all, m_one = min(oracle_sample, batch), min(oracle_sample_one, batch)
+    span_all = int(offs[m_all - 1] + int(sizes[m_all - 1]) ** 2)
+    t0 = time.perf_counter()
+    Xo, io, jo, ro = oracle.gj_invert_batched(sizes[:m_all], offs[:m_all], packed[:span_all])
+    t_all = (time.perf_counter() - t0) * cube.sum() / cube[:m_all].sum()
+    span_one = int(offs[m_one - 1] + int(sizes[m_one - 1]) ** 2)
+    t0 = time.perf_counter()
+    oracle.gj_invert_batched(sizes[:m_one], offs[:m_one], packed[:span_one], nthreads=1)
+    t_one = (time.perf_counter() - t0) * cube.sum() / cube[:m_one].sum()
+    npiv = int(poff[m_all - 1] + sizes[m_all - 1])
+    same = bool(X[:span_all].cpu().numpy().tobytes() == Xo[:span_all].tobytes()
+                and np.array_equal(ip[:npiv].cpu().numpy(), io) and np.array_equal(jp[:npiv].cpu().numpy(), jo))
     return {
         "batch": batch,
         "ms": round(ms, 3),
         "inversions_per_s": round(batch / (ms * 1e-3), 1),
-        "fp64_tflops": round(flops / (ms * 1e-3) / 1e12, 3),
-        "frac_of_fp64_peak": round(flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "fp64_tflops": round(tflops, 3),
+        "roofline": {"bound": "alu", "kernel": "gj_onchip_kernel (FP64, every class)",
+                     "achieved": round(tflops, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tflops / FP64_PEAK_TFLOPS, 4),
+                     "alg_flop": flops, "note": "n^3 fma per member; pivot-search compares not counted"},
         "singular_flagged": int((codes == 1).sum()),
         "singular_planted": int(len(singular)),
         "other_codes": int(((codes != 0) & (codes != 1)).sum()),
+        "oracle": {"all_cores_inversions_per_s": round(batch / t_all, 1),
+                   "one_core_inversions_per_s": round(batch / t_one, 1),
+                   "threads": oracle.host_threads(),
+                   "sample": f"first {m_all} members on all cores, first {m_one} on one core, "
+                             "scaled by sum n^3",
+                   "gpu_bitwise_equal_on_sample": same},
     }
 
 
@@ -301,21 +484,35 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
                          device="cuda")
         gj.gj_invert(A, X, ip, jp, res, opts, ws)
         torch.cuda.synchronize()
-        e = _events(2 * reps, stream)
+        e = _events(4 * reps, stream)
         for k in range(reps):
-            e[2 * k].record()
-            gj.gj_invert(A, X, ip, jp, res, opts, ws)
-            e[2 * k + 1].record()
+            so = gj.make_opts(precision=prec, flags=flags,
+                              step_events=(ctypes_ptr(e[4 * k + 1]), ctypes_ptr(e[4 * k + 2])))
+            e[4 * k].record()
+            gj.gj_invert(A, X, ip, jp, res, so, ws)
+            e[4 * k + 3].record()
         torch.cuda.synchronize()
-        ms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+        best = min(range(reps), key=lambda k: e[4 * k].elapsed_time(e[4 * k + 3]))
+        ms = e[4 * best].elapsed_time(e[4 * best + 3])
+        steps_ms = e[4 * best + 1].elapsed_time(e[4 * best + 2])
         r = gj.results_to_dicts(res)[0]
         del ws
         R = gj.gj_dgemm(A, X, gamma=1.0, alpha=-1.0)
         resid = float(torch.linalg.norm(R) / (torch.linalg.norm(A) * torch.linalg.norm(X)))
         del R
+        # the elimination's step kernel: each launch reads and writes the
+        # whole n x n array once (16 n^2 B in FP64, 8 n^2 B in FP32)
+        esz = 8 if prec == gj.GJ_PREC_FP64 else 4
+        gbs = 2.0 * esz * n * n * n / (steps_ms * 1e-3) / 1e9
         out[name] = {"ms": round(ms, 1), "inversions_per_s": round(1e3 / ms, 4), "code": r["code"],
                      "refine_iters": r["refine_iters"], "logabsdet": r["logabsdet"],
-                     "det_sign": r["det_sign"], "resid": resid}
+                     "det_sign": r["det_sign"], "resid": resid,
+                     "elimination_ms": round(steps_ms, 1),
+                     "step_roofline": {"bound": "hbm", "kernel": "gj_big_step (%s)" % ("FP64" if esz == 8 else "FP32"),
+                                       "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                       "alg_bytes_per_launch": 2 * esz * n * n,
+                                       "per_launch_us": round(steps_ms * 1e3 / n, 2)}}
         Xs[name] = X
     d = float(torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"]))
     out["refined_vs_plain_rel_frobenius"] = d
@@ -341,6 +538,54 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
                             "ms": round(gms, 3), "achieved": round(tflops, 2),
                             "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                             "frac": round(tflops / FP64_PEAK_TFLOPS, 4)}
+    del Xs, X, R, D, A
+    torch.cuda.empty_cache()
+    out["cross_check_2048"] = oracle_cross_check_2048()
+    return out
+
+
+def oracle_cross_check_2048(n: int = 2048, cond: float = 1e6):
+    """The 2048 instance of the conditioned workload (seed offset 40, built on
+    the host): the plain and refined GPU inverses against the FP64 oracle and
+    against a reference inverse (Newton steps from the oracle's inverse with
+    an exactly formed residual), with the oracle timed on all host cores and
+    on one."""
+    import torch
+    import oracle
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    A_h = inputs.single_conditioned(n, cond, offset=40)
+    A = torch.from_numpy(A_h).cuda()
+    gpu = {}
+    for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
+        X, ip, jp, res = gj.gj_invert(A, opts=gj.make_opts(precision=prec))
+        torch.cuda.synchronize()
+        gpu[name] = (X.cpu().numpy(), ip.cpu().numpy(), jp.cpu().numpy(), gj.results_to_dicts(res)[0])
+    t0 = time.perf_counter()
+    Xo, io, jo, ro = oracle.gj_invert_f64_par(A_h)
+    t_all = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Xt = oracle.inverse_truth(A_h, Xo)
+    t_truth = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.gj_first_steps(A_h, 128)
+    t_one = (time.perf_counter() - t0) * n / 128
+    err_o = _rel(Xo, Xt)
+    out = {"n": n, "cond": cond, "fp64_oracle_forward_error_vs_reference": err_o}
+    for name, (Xg, ig, jg, r) in gpu.items():
+        out[name] = {"code": r["code"], "refine_iters": r["refine_iters"],
+                     "rel_frobenius_vs_fp64_oracle": _rel(Xg, Xo),
+                     "rel_forward_error_vs_reference": _rel(Xg, Xt),
+                     "logabsdet_minus_closed_form": r["logabsdet"] - inputs.closed_form_logdet(n, cond)}
+    Xg, ig, jg, r = gpu["plain_fp64"]
+    out["plain_fp64"]["bitwise_equal_to_oracle"] = bool(
+        Xg.tobytes() == Xo.tobytes() and np.array_equal(ig, io) and np.array_equal(jg, jo)
+        and r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"])
+    out["refined_error_over_oracle_error"] = out["fp32_refined"]["rel_forward_error_vs_reference"] / err_o
+    out["oracle"] = {"all_cores_s": round(t_all, 2), "threads": oracle.host_threads(),
+                     "one_core_s": round(t_one, 1), "reference_inverse_s": round(t_truth, 2),
+                     "sample": "all cores: the whole inversion; one core: the first 128 of 2048 "
+                               "steps, scaled by 16"}
     return out
 
 
@@ -519,25 +764,24 @@ def ctypes_ptr(event):
     return event.cuda_event
 
 
-def cpu_baseline(n: int = 4096, sample_steps: int = 256):
-    """The FP64 oracle (single-threaded C) on the same 4096 input for its
-    first ``sample_steps`` steps; every step of the in-place elimination does
-    the same n(n-1) updates, so the full inversion takes n/sample_steps times
-    as long (the shrinking pivot search makes this a slight overestimate)."""
-    import oracle
+def cpu_baseline(n: int = 4096, all_steps: int = 512, one_steps: int = 64):
+    """The FP64 oracle on the same 4096 input, timed on all host cores (its
+    OpenMP form: each step's rows shared among threads, bitwise the serial
+    oracle) and on one core (the serial oracle), each over the first steps
+    of the run and scaled by n / steps (every step does the same n(n-1)
+    updates; the shrinking search makes this a slight overestimate)."""
     from paper_1401_7962_amd import inputs
     A = inputs.single_dominant(n)
-    t0 = time.perf_counter()
-    oracle.gj_first_steps(A, sample_steps)
-    dt = time.perf_counter() - t0
-    full = dt * n / sample_steps
+    r = _oracle_sample_rate(A, all_steps, one_steps)
+    info = host_info()
     return {
-        "value": 1.0 / full,
+        "value": round(1.0 / r["all_cores_s_per_inversion"], 5),
         "unit": "inversions/s",
-        "cores": 1,
+        "cores": r["threads"],
         "kind": "oracle",
-        "sample": f"first {sample_steps} of {n} elimination steps of the {n}x{n} input "
-                  f"({dt:.1f} s), scaled by {n}/{sample_steps}",
+        "sample": r["sample"] + f" of the {n}x{n} input",
+        "cpu_model": info["cpu_model"],
+        "single_core": {"value": round(1.0 / r["one_core_s_per_inversion"], 5), "cores": 1},
     }
 
 
@@ -620,6 +864,7 @@ def main():
         },
         "checks": {"resid": head["resid"], "logabsdet": head["logabsdet"],
                    "det_sign": head["det_sign"]},
+        "fp32_refined_same_input": head["refined"],
     }
     if not args.headline_only:
         extras = {}
@@ -647,8 +892,10 @@ def main():
         print("bench: blocked elimination done", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["extras"] = extras
+        out["host"] = host_info()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.n)
+        print("bench: cpu baseline done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
