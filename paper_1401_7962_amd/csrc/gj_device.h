@@ -71,7 +71,8 @@ __device__ __forceinline__ T div_pivot_fast(T x, T p, T y, bool p_ok, bool &slow
     const T q = x * y;
     const T r = Num<T>::fma_(-p, q, x);
     const T res = (ax == (T)0) ? q : Num<T>::fma_(r, y, q);
-    slow |= !((ax == (T)0) || (p_ok && ax >= DivRange<T>::lo() && ax <= DivRange<T>::hi()));
+    // bitwise operators: no short-circuit branches on the common path
+    slow |= !((ax == (T)0) | (p_ok & (ax >= DivRange<T>::lo()) & (ax <= DivRange<T>::hi())));
     return res;
 }
 

@@ -13,9 +13,10 @@
 //      ties to the lowest row then column);
 //   2. singular / non-finite test against the zero threshold (Obs. 2);
 //   3. rows k,r and columns k,c are swapped physically: the owners of the four
-//      lines stage them in LDS, together with the pivot row already divided by
-//      the pivot (eq. 14, correctly rounded division, slot (k,k) = 1/p) and
-//      the pivot column (the multipliers a_ik);
+//      lines stage them in LDS (the pivot row with slot k = 1, the pivot
+//      column holding the multipliers a_ik), and every thread divides its own
+//      entries of the pivot row by the pivot (eq. 14, correctly rounded, so
+//      slot (k,k) becomes 1/p);
 //   4. every element takes one fma with the staged row and column (eq. 15);
 //      the pivot row is then overwritten with its scaled values;
 //   5. while the new values are in registers, each thread scans its part of
@@ -37,7 +38,7 @@ struct CoreLds {
     // Positions >= n (padding) hold 0 in every array and in the registers: the
     // swap maps fix them, so padding lanes stage 0 onto 0, and a 0 never wins
     // the pivot search.  No per-element bounds test is needed.
-    T prow[N];     // new pivot row, divided by the pivot
+    T prow[N + 1]; // new pivot row, not yet divided (slot k = 1); the pivot in slot N
     T pcol[N];     // new pivot column (multipliers)
     T newr[N];     // new row r  (= old row k, columns swapped)
     T newc[N];     // new column c (= old column k, rows swapped)
@@ -45,8 +46,8 @@ struct CoreLds {
     int32_t h[N];  // destination column of working column j
     int32_t ip[N]; // pivot sequence, written out once at the end (a global
     int32_t jp[N]; // store inside the step loop would make every barrier wait for it)
-    Cand<T> red[NW];
-    T pv;          // the signed pivot of the current step (for the determinant)
+    T red_v[NW];   // each wavefront's largest |a| and its position key
+    uint32_t red_k[NW];
 };
 
 template <int NW>
@@ -60,28 +61,104 @@ __device__ inline void group_sync() {
     }
 }
 
-// Reduce (|v|, key) over the group.  Every thread ends with the same winner.
+// Largest of the 64 lanes' values, in every lane (values are |a| >= 0).
+template <typename T, int CTRL>
+__device__ inline T dpp_move(T x) {
+    uint32_t w[Lanes<T>::W];
+    Lanes<T>::split(x, w);
+#pragma unroll
+    for (int i = 0; i < Lanes<T>::W; ++i) w[i] = dpp_u32<CTRL>(w[i]);
+    return Lanes<T>::join(w);
+}
+
+template <typename T>
+__device__ inline T maxT(T a, T b) { return a > b ? a : b; }
+
+template <typename T, bool P32>
+__device__ inline T perm_max(T x) {
+    uint32_t w[Lanes<T>::W], a[Lanes<T>::W], b[Lanes<T>::W];
+    Lanes<T>::split(x, w);
+#pragma unroll
+    for (int i = 0; i < Lanes<T>::W; ++i) {
+        auto p = P32 ? __builtin_amdgcn_permlane32_swap(w[i], w[i], false, false)
+                     : __builtin_amdgcn_permlane16_swap(w[i], w[i], false, false);
+        a[i] = p[0];
+        b[i] = p[1];
+    }
+    return maxT(Lanes<T>::join(a), Lanes<T>::join(b));
+}
+
+template <typename T>
+__device__ inline T wave_max(T m) {
+    m = maxT(m, dpp_move<T, 0xB1>(m));    // quad_perm [1,0,3,2]
+    m = maxT(m, dpp_move<T, 0x4E>(m));    // quad_perm [2,3,0,1]
+    m = maxT(m, dpp_move<T, 0x141>(m));   // row_half_mirror
+    m = maxT(m, dpp_move<T, 0x140>(m));   // row_mirror
+    m = perm_max<T, false>(m);
+    m = perm_max<T, true>(m);
+    return m;
+}
+
+// Smallest of the 64 lanes' keys, in every lane.
+__device__ inline uint32_t wave_min_u32(uint32_t x) {
+    x = min(x, dpp_u32<0xB1>(x));
+    x = min(x, dpp_u32<0x4E>(x));
+    x = min(x, dpp_u32<0x141>(x));
+    x = min(x, dpp_u32<0x140>(x));
+    auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    x = min(p[0], p[1]);
+    auto q = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return min(q[0], q[1]);
+}
+
+// Reduce (|a|, key) over the group: the largest value, ties to the smallest
+// key (the first in row-major order).  The wavefront reduces the value
+// alone; a ballot names the lanes that hold it, and only when several do
+// are their keys reduced too.  The wavefronts' winners meet in LDS.  Every
+// thread ends with the same winner.
 template <typename T, int N, int NW>
 __device__ inline void group_argmax(Cand<T> &c, CoreLds<T, N, NW> &L, int t) {
-    wave_argmax(c);
+    const T m = wave_max(c.v);
+    const bool have = (c.v == m) & (c.key != 0xFFFFFFFFu);
+    const unsigned long long eq = __ballot(have);
+    uint32_t key;
+    if (eq == 0ull) {
+        key = 0xFFFFFFFFu;                                  // nothing left to search
+    } else if ((eq & (eq - 1ull)) == 0ull) {                // one lane holds the maximum
+        key = (uint32_t)__builtin_amdgcn_readlane((int)c.key, __builtin_ctzll(eq));
+    } else {                                                // equal maxima: the smallest key
+        key = wave_min_u32(have ? c.key : 0xFFFFFFFFu);
+    }
     if constexpr (NW > 1) {
-        const int lane = t & (kWave - 1), w = t / kWave;
-        if (lane == 0) L.red[w] = c;
+        const int w = t / kWave;
+        if ((t & (kWave - 1)) == 0) {
+            L.red_v[w] = m;
+            L.red_k[w] = key;
+        }
         __syncthreads();
-        Cand<T> best = L.red[0];
+        T bv = L.red_v[0];
+        uint32_t bk = L.red_k[0];
 #pragma unroll
         for (int x = 1; x < NW; ++x) {
-            const Cand<T> o = L.red[x];
-            cand_take(best, o.v, o.key);
+            const T ov = L.red_v[x];
+            const uint32_t ok = L.red_k[x];
+            const bool take = (ov > bv) | ((ov == bv) & (ok < bk));
+            bv = take ? ov : bv;
+            bk = take ? ok : bk;
         }
-        c = best;
+        c.v = bv;
+        c.key = bk;
+    } else {
+        c.v = m;
+        c.key = key;
     }
 }
 
 // Scan this thread's part of the trailing block (rows and columns > k) in
 // row-major order; strict '>' keeps the first maximum (padding holds 0 and
-// never wins).  Register blocks whose rows (or columns) are all pivoted are
-// skipped: the test is the same for the whole wavefront.  The candidate
+// never wins).  Register rows whose rows are all pivoted are skipped (a
+// wavefront-uniform branch); within a row the pivoted columns are masked per
+// lane, which costs less than a branch per element.  The candidate
 // carries |a| and the position; the owners of the winning row recover the
 // signed pivot when they stage it.  The winning slot is tracked as the
 // compile-time code a*EB+b, so no per-element key stays live across steps,
@@ -106,7 +183,6 @@ __device__ __forceinline__ void scan_argmax(const T (&v)[EA][EB], int k, int tr,
         const int h = a % NCH;
 #pragma unroll
         for (int b = 0; b < EB; ++b) {
-            if (b * TC + TC - 1 <= k) continue;    // every column of this block pivoted
             const T ax = M::abs_(v[a][b]);
             const bool gt = rok & cok[b] & (ax > rbest[h]);
             rbest[h] = gt ? ax : rbest[h];
@@ -194,98 +270,69 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
         const int ar = r / TR, trr = r % TR, ak = k / TR, trk = k % TR;
         const int bc = cc / TC, tcc = cc % TC, bk = k / TC, tck = k % TC;
 
-        // Stage the four swapped lines and the scaled pivot row (eq. 14).
-        // Each line is written in its natural order and then the one or two
-        // entries that the swap moves are written again.  A line written by
-        // lanes of one wavefront only (the rows) relies on its writes landing
-        // in program order; for the columns, written by lanes of every
-        // wavefront, the natural write of a moved position is left out.
-        // Row r: its owners extract it (uniform branches on ar), take the
-        // signed pivot from the lane that holds column c, and divide.
-        if (tr == trr) {
+        // Stage the four swapped lines in LDS.  Each entry goes straight to
+        // its slot after the swaps (rows r,k and columns c,k exchanged): the
+        // slots form a permutation, so no slot is written by two wavefronts
+        // and the readers need no fix-ups.  Row r goes out unscaled; its
+        // pivot goes to slot N and its pivot slot (column k after the swap)
+        // is set to 1, so that after the barrier every thread divides its own
+        // entries by the pivot (eq. 14) and 1/p, the pivot slot of D, comes
+        // out of the same correctly rounded division.  (Dividing here, in the
+        // one wavefront that owns row r, would keep the others waiting.)
+        const bool lane_r = (tr == trr), lane_k = (tr == trk);
+        const bool lane_c = (tc == tcc), lane_ck = (tc == tck);
+        if (lane_r) {
 #pragma unroll
             for (int a = 0; a < EA; ++a)
                 if (a == ar) {
-                    T xc = (T)0, xk = (T)0;
 #pragma unroll
                     for (int b = 0; b < EB; ++b) {
-                        if (b == bc) xc = v[a][b];
+                        int j = b * TC + tc;
+                        j = (lane_ck & (b == bk)) ? cc : j;
+                        j = (lane_c & (b == bc)) ? N : j;
+                        L.prow[j] = v[a][b];
                     }
-                    // the pivot sits in lane (trr, tcc) of this row group
-                    const int src = (trr * TC + tcc) & (kWave - 1);
-                    T p;
-                    if constexpr (sizeof(T) == 8) {
-                        const int lo = __builtin_amdgcn_readlane(__double2loint(xc), src);
-                        const int hi = __builtin_amdgcn_readlane(__double2hiint(xc), src);
-                        p = __hiloint2double(hi, lo);
-                    } else {
-                        p = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(xc), src));
-                    }
-                    const T y = M::one() / p;   // RN(1/p): the pivot slot, and the division seed
-                    const bool p_ok = div_pivot_ok(p);
-                    bool slow = false;
-                    T q[EB];
-#pragma unroll
-                    for (int b = 0; b < EB; ++b) q[b] = div_pivot_fast(v[a][b], p, y, p_ok, slow);
-                    if (slow) {   // operands outside the corrected-quotient range
-#pragma unroll
-                        for (int b = 0; b < EB; ++b) q[b] = div_pivot(v[a][b], p, y, p_ok);
-                    }
-#pragma unroll
-                    for (int b = 0; b < EB; ++b) {
-                        L.prow[b * TC + tc] = q[b];
-                        if (b == bk) xk = q[b];
-                    }
-                    // the column swap: column k's quotient goes to c, 1/p to k
-                    if (tc == tck) L.prow[cc] = xk;
-                    if (tc == tcc) {
-                        L.prow[k] = y;
-                        L.pv = p;
-                    }
+                    if (lane_c) L.prow[k] = M::one();   // after the write above, same lane
                 }
         }
-        if (tr == trk) {                       // old row k -> row r, columns swapped
+        if (lane_k) {                          // old row k -> row r, columns swapped
 #pragma unroll
             for (int a = 0; a < EA; ++a)
                 if (a == ak) {
-                    T xk = (T)0, xc = (T)0;
 #pragma unroll
                     for (int b = 0; b < EB; ++b) {
-                        L.newr[b * TC + tc] = v[a][b];
-                        if (b == bk) xk = v[a][b];
-                        if (b == bc) xc = v[a][b];
+                        int j = b * TC + tc;
+                        j = (lane_ck & (b == bk)) ? cc : j;
+                        j = (lane_c & (b == bc)) ? k : j;
+                        L.newr[j] = v[a][b];
                     }
-                    if (tc == tck) L.newr[cc] = xk;
-                    if (tc == tcc) L.newr[k] = xc;
                 }
         }
-        if (tc == tcc) {                       // the multipliers, rows swapped
+        if (lane_c | lane_ck) {
+            int ri[EA];                        // slot of each register row after the row swap
 #pragma unroll
-            for (int b = 0; b < EB; ++b)
-                if (b == bc) {
-                    T vk = (T)0;
+            for (int a = 0; a < EA; ++a) {
+                int i = a * TR + tr;
+                i = (lane_k & (a == ak)) ? r : i;
+                i = (lane_r & (a == ar)) ? k : i;
+                ri[a] = i;
+            }
+            if (lane_c) {                      // the multipliers
 #pragma unroll
-                    for (int a = 0; a < EA; ++a) {
-                        if (a != ar || tr != trr) L.pcol[a * TR + tr] = v[a][b];
-                        if (a == ak) vk = v[a][b];
+                for (int b = 0; b < EB; ++b)
+                    if (b == bc) {
+#pragma unroll
+                        for (int a = 0; a < EA; ++a) L.pcol[ri[a]] = v[a][b];
                     }
-                    if (tr == trk) L.pcol[r] = vk;
-                }
-        }
-        if (tc == tck) {                       // old column k -> column c, rows swapped
+            }
+            if (lane_ck) {                     // old column k -> column c
 #pragma unroll
-            for (int b = 0; b < EB; ++b)
-                if (b == bk) {
-                    T vk = (T)0, vr = (T)0;
+                for (int b = 0; b < EB; ++b)
+                    if (b == bk) {
 #pragma unroll
-                    for (int a = 0; a < EA; ++a) {
-                        if ((a != ar || tr != trr) && (a != ak || tr != trk)) L.newc[a * TR + tr] = v[a][b];
-                        if (a == ak) vk = v[a][b];
-                        if (a == ar) vr = v[a][b];
+                        for (int a = 0; a < EA; ++a) L.newc[ri[a]] = v[a][b];
                     }
-                    if (tr == trk) L.newc[r] = vk;
-                    if (tr == trr) L.newc[k] = vr;
-                }
+            }
         }
         if (t == 0) {
             L.ip[k] = r;
@@ -294,13 +341,15 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
         group_sync<NW>();
 
         // eq. 13, in step order (every lane keeps the same product)
-        det.mul(L.pv);
+        const T p = L.prow[N];
+        det.mul(p);
         if (r != k) det.sign = -det.sign;
         if (cc != k) det.sign = -det.sign;
 
         // install the swapped row r and column c; clear column k (it becomes
-        // fma(-q, 1/p, 0) below, the D column of eq. 15)
-        if (tr == trr) {
+        // fma(-q, 1/p, 0) below, the D column of eq. 15; when c = k the clear
+        // comes last)
+        if (lane_r) {
 #pragma unroll
             for (int a = 0; a < EA; ++a)
                 if (a == ar) {
@@ -308,7 +357,7 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
                     for (int b = 0; b < EB; ++b) v[a][b] = L.newr[b * TC + tc];
                 }
         }
-        if (tc == tcc) {
+        if (lane_c) {
 #pragma unroll
             for (int b = 0; b < EB; ++b)
                 if (b == bc) {
@@ -316,7 +365,7 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
                     for (int a = 0; a < EA; ++a) v[a][b] = L.newc[a * TR + tr];
                 }
         }
-        if (tc == tck) {
+        if (lane_ck) {
 #pragma unroll
             for (int b = 0; b < EB; ++b)
                 if (b == bk) {
@@ -324,12 +373,22 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
                     for (int a = 0; a < EA; ++a) v[a][b] = (T)0;
                 }
         }
-        // eq. 15 for every row, then the pivot row takes its scaled values
-        T q[EA], pr[EB];
+        // eq. 14 on this thread's columns of the pivot row; eq. 15 for every
+        // row, then the pivot row takes its scaled values
+        const T y = M::one() / p;
+        const bool p_ok = div_pivot_ok(p);
+        T q[EA], pr[EB], xr[EB];
+#pragma unroll
+        for (int b = 0; b < EB; ++b) xr[b] = L.prow[b * TC + tc];
 #pragma unroll
         for (int a = 0; a < EA; ++a) q[a] = L.pcol[a * TR + tr];
+        bool slow = false;
 #pragma unroll
-        for (int b = 0; b < EB; ++b) pr[b] = L.prow[b * TC + tc];
+        for (int b = 0; b < EB; ++b) pr[b] = div_pivot_fast(xr[b], p, y, p_ok, slow);
+        if (slow) {   // operands outside the corrected-quotient range
+#pragma unroll
+            for (int b = 0; b < EB; ++b) pr[b] = div_pivot(xr[b], p, y, p_ok);
+        }
 #pragma unroll
         for (int a = 0; a < EA; ++a)
 #pragma unroll
@@ -409,8 +468,9 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 // an atomic queue until it is empty; tasks are ordered by decreasing cost on
 // the host.  With mats == nullptr the kernel inverts the single matrix passed
 // by value (workgroup 0, KIND 0).
+// At least two wavefronts per SIMD: the register budget stays within 256.
 template <typename T, int KIND, int E>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gj_onchip_kernel(const MatDesc *__restrict__ mats, const OnchipTask *__restrict__ tasks,
                  int ntasks, uint32_t *__restrict__ queue, const MatDesc single,
                  const double *__restrict__ A, double *__restrict__ X, int32_t *__restrict__ ipiv,
