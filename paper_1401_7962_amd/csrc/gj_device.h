@@ -72,7 +72,8 @@ __device__ __forceinline__ T div_pivot_fast(T x, T p, T y, bool p_ok, bool &slow
     const T r = Num<T>::fma_(-p, q, x);
     const T res = (ax == (T)0) ? q : Num<T>::fma_(r, y, q);
     // bitwise operators: no short-circuit branches on the common path
-    slow |= !((ax == (T)0) | (p_ok & (ax >= DivRange<T>::lo()) & (ax <= DivRange<T>::hi())));
+    slow |= ((int)(ax == (T)0) | ((int)p_ok & (int)(ax >= DivRange<T>::lo()) &
+                                  (int)(ax <= DivRange<T>::hi()))) == 0;
     return res;
 }
 
