@@ -544,6 +544,34 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
     return out
 
 
+def bench_gemm_f64(n: int = 8192, reps: int = 3):
+    """The refinement's product alone: D = X R for n x n FP64 operands (the
+    Newton-Schulz update X (I - A X) of the conditioned workload has this
+    shape), timed with HIP events; for counter runs (MFMA busy cycles)."""
+    import torch
+    import paper_1401_7962_amd as gj
+    g = torch.Generator(device="cuda")
+    g.manual_seed(8192)
+    X = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    R = torch.randn(n, n, dtype=torch.float64, device="cuda", generator=g)
+    D = torch.empty_like(X)
+    gj.gj_dgemm(X, R, D=D)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e = _events(2 * reps, stream)
+    for k in range(reps):
+        e[2 * k].record()
+        gj.gj_dgemm(X, R, D=D)
+        e[2 * k + 1].record()
+    torch.cuda.synchronize()
+    gms = min(e[2 * k].elapsed_time(e[2 * k + 1]) for k in range(reps))
+    tflops = 2.0 * n ** 3 / (gms * 1e-3) / 1e12
+    return {"n": n, "calls": reps + 1, "ms": round(gms, 3),
+            "roofline": {"bound": "mfma", "kernel": "gemm_f64_kernel (n x n x n)",
+                         "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "flop_per_call": 2.0 * n ** 3}}
+
+
 def oracle_cross_check_2048(n: int = 2048, cond: float = 1e6):
     """The 2048 instance of the conditioned workload (seed offset 40, built on
     the host): the plain and refined GPU inverses against the FP64 oracle and
@@ -792,7 +820,8 @@ LEGS = {"latency_small": lambda: bench_latency_small(),
         "solve_4096": lambda: bench_solve(),
         "pivot_rules": lambda: bench_pivot_rules(),
         "accuracy_exact_4096": lambda: bench_accuracy_exact(),
-        "blocked": lambda: bench_blocked()}
+        "blocked": lambda: bench_blocked(),
+        "gemm_f64_8192": lambda: bench_gemm_f64()}
 
 
 def main():
