@@ -9,7 +9,8 @@ is compared by its forward error against the long-double oracle, which may be
 at most 4x the FP64 oracle's own plus 1e-15 (relative Frobenius; the same bar
 as the refined path's, R-16), up to order 520 (the long-double oracle's time);
 at every order its residual ||A X - I||_F / (||A||_F ||X||_F) may be at most
-4x the FP64 oracle's own plus 1e-16, and X within 1e-11 of the oracle's.  With
+4x the FP64 oracle's own plus 1e-16, and X within 1e-12 of the oracle's (the
+inputs have cond <= 1e4).  With
 a single panel nothing is delayed and X must be the oracle's bit for bit.
 """
 import numpy as np
@@ -49,9 +50,11 @@ def _resid(A, X):
 
 
 def _accurate(A, X, Xo, where):
-    """X from the blocked elimination against the FP64 oracle's Xo."""
+    """X from the blocked elimination against the FP64 oracle's Xo: the inputs
+    here have cond <= 1e4, for which the bar is 1e-12 relative Frobenius."""
+    assert np.linalg.cond(A) <= 1e4, where
     assert _resid(A, X) <= 4 * _resid(A, Xo) + 1e-16, where
-    assert _rel(X, Xo) <= 1e-11, where
+    assert _rel(X, Xo) <= 1e-12, where
     if A.shape[0] <= 520:
         Xt, _, _, _ = oracle.gj_invert_f80(A)
         err, err_o = _rel(X, Xt), _rel(Xo, Xt)
