@@ -281,6 +281,19 @@ gj_status gj_dgemm(int32_t M, int32_t N, int32_t K, double alpha, const double *
                    const double *B, int64_t ldb, double beta, const double *C, int64_t ldc,
                    double gamma, double *D, int64_t ldd, void *stream);
 
+/*
+ * gj_sgemm -- the same product in FP32 on the matrix cores
+ * (v_mfma_f32_16x16x4f32, FP32 accumulation):
+ *     D = alpha * (A B) + beta * C + gamma * I       (row-major, FP32)
+ * Shapes, leading dimensions, aliasing and errors as for gj_dgemm.  Paper:
+ * not in the paper; the delayed updates of the FP32 elimination with
+ * GJ_FLAG_BLOCKED (the panel's left factors of section 1 grouped into one
+ * product) are made of these products.
+ */
+gj_status gj_sgemm(int32_t M, int32_t N, int32_t K, float alpha, const float *A, int64_t lda,
+                   const float *B, int64_t ldb, float beta, const float *C, int64_t ldc,
+                   float gamma, float *D, int64_t ldd, void *stream);
+
 /* Text for a gj_status value or a GJ_RES_* code given as (100 + code). */
 const char *gj_status_string(int32_t code);
 

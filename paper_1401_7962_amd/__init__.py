@@ -94,6 +94,9 @@ def load_library(path: str = LIB_PATH):
     D = ctypes.c_double
     lib.gj_dgemm.argtypes = [I32, I32, I32, D, P, I64, P, I64, D, P, I64, D, P, I64, P]
     lib.gj_dgemm.restype = I32
+    F = ctypes.c_float
+    lib.gj_sgemm.argtypes = [I32, I32, I32, F, P, I64, P, I64, F, P, I64, F, P, I64, P]
+    lib.gj_sgemm.restype = I32
     lib.gj_onchip_max_n.argtypes = [I32]
     lib.gj_onchip_max_n.restype = I32
     _lib = lib
@@ -101,7 +104,7 @@ def load_library(path: str = LIB_PATH):
 
 
 EXPORTS = ("gj_invert", "gj_invert_noalloc", "gj_invert_batched", "gj_det", "gj_solve",
-           "gj_workspace_size", "gj_status_string", "gj_onchip_max_n", "gj_dgemm")
+           "gj_workspace_size", "gj_status_string", "gj_onchip_max_n", "gj_dgemm", "gj_sgemm")
 
 # size of gj_invert_noalloc's built-in scratch array (GJ_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -286,6 +289,31 @@ def gj_dgemm(A, B, C=None, D=None, alpha=1.0, beta=0.0, gamma=0.0, stream=None):
     if D is None:
         D = torch.empty((M, N), dtype=torch.float64, device=A.device)
     st = lib.gj_dgemm(M, N, K, float(alpha), _ptr(A), A.stride(0), _ptr(B), B.stride(0),
+                      float(beta), _ptr(C) if C is not None else None,
+                      C.stride(0) if C is not None else N, float(gamma), _ptr(D), D.stride(0),
+                      _stream_ptr(stream))
+    _check(st)
+    return D
+
+
+def gj_sgemm(A, B, C=None, D=None, alpha=1.0, beta=0.0, gamma=0.0, stream=None):
+    """D = alpha A B + beta C + gamma I on the FP32 matrix cores (2-D float32
+    CUDA tensors, unit column stride)."""
+    import torch
+    lib = load_library()
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise GJError("inner dimensions differ")
+    for name, T in (("A", A), ("B", B), ("C", C), ("D", D)):
+        if T is not None and (T.dtype != torch.float32 or not T.is_cuda or T.dim() != 2
+                              or T.stride(1) != 1):
+            raise GJError(f"{name} must be a 2-D float32 CUDA tensor with unit column stride")
+    if D is None:
+        D = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    if D.shape != (M, N) or (C is not None and C.shape != (M, N)):
+        raise GJError("C and D must be M x N")
+    st = lib.gj_sgemm(M, N, K, float(alpha), _ptr(A), A.stride(0), _ptr(B), B.stride(0),
                       float(beta), _ptr(C) if C is not None else None,
                       C.stride(0) if C is not None else N, float(gamma), _ptr(D), D.stride(0),
                       _stream_ptr(stream))

@@ -1493,6 +1493,26 @@ gj_status gj_dgemm(int32_t M, int32_t N, int32_t K, double alpha, const double *
     }
 }
 
+gj_status gj_sgemm(int32_t M, int32_t N, int32_t K, float alpha, const float *A, int64_t lda,
+                   const float *B, int64_t ldb, float beta, const float *C, int64_t ldc,
+                   float gamma, float *D, int64_t ldd, void *stream) {
+    try {
+        if (M < 0 || N < 0 || K < 0 || !D || ldd < N) return GJ_E_INVALID_ARG;
+        if (K > 0 && (!A || !B || lda < K || ldb < N)) return GJ_E_INVALID_ARG;
+        if (beta != 0.0f && (!C || ldc < N)) return GJ_E_INVALID_ARG;
+        GemmArgsT<float> g;
+        std::memset(&g, 0, sizeof(g));
+        g.M = M; g.N = N; g.K = K;
+        g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+        g.alpha = alpha; g.beta = beta; g.gamma = gamma;
+        hipError_t e = launch_gemm_f32(g, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e);
+        return GJ_OK;
+    } catch (...) {
+        return GJ_E_HIP;
+    }
+}
+
 int32_t gj_onchip_max_n(int32_t precision) {
     (void)precision;
     return kOnchipMax;

@@ -1,4 +1,6 @@
-// gemm.hip -- FP64 GEMM on the matrix cores (v_mfma_f64_16x16x4f64).
+// gemm.hip -- GEMM on the matrix cores: FP64 (v_mfma_f64_16x16x4f64) and
+// FP32 (v_mfma_f32_16x16x4f32, for the delayed updates of the FP32
+// elimination).
 //
 //   D = alpha * (A B) + beta * C + gamma * I        (row-major, FP64)
 //
@@ -31,6 +33,26 @@ constexpr int LDA_S = BM + 2;  // LDS row pitch (doubles), padded against bank c
 constexpr int LDB_S = BN + 2;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 MFMA step and the accumulator layout of each precision:
+// register r of lane l holds column l % 16 and row row(l / 16, r) of the
+// 16 x 16 block (FP64: l/16 + 4r; FP32: 4 (l/16) + r).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    using acc_t = d4;
+    __device__ static acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct Mfma<float> {
+    using acc_t = f4;
+    __device__ static acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
 
 // One 128 x 128 tile of D.  `b` is the tile index within the problem,
 // `part` the slot of its norm partial.
@@ -40,9 +62,11 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 // the other, and a single barrier per slice separates the two roles.  Global
 // reads go through the global address space (not FLAT), so that waiting for
 // an LDS read never waits for the prefetch of the next slice as well.
-__device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
-    __shared__ double As[2][BK][LDA_S];  // As[buf][k][m]
-    __shared__ double Bs[2][BK][LDB_S];  // Bs[buf][k][n]
+template <typename T>
+__device__ __forceinline__ void gemm_tile(const GemmArgsT<T> &g, int b, int part) {
+    using MF = Mfma<T>;
+    __shared__ T As[2][BK][LDA_S];  // As[buf][k][m]
+    __shared__ T Bs[2][BK][LDB_S];  // Bs[buf][k][n]
     __shared__ double s_red[NTH / kWave];
 
     const int tiles_n = (g.N + BN - 1) / BN;
@@ -51,31 +75,33 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const gptr<const double> gA = glb(g.A), gB = glb(g.B);
+    const gptr<const T> gA = glb(g.A), gB = glb(g.B);
 
-    d4 acc[4][4];
+    typename MF::acc_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = (T)0;
 
     // global -> register staging: A tile 128 x 16 (thread: row t/2, 8 k's),
     // B tile 16 x 128 (thread: k t/16, 8 columns)
     const int a_row = t >> 1, a_k0 = (t & 1) * 8;
     const int b_k = t >> 4, b_c0 = (t & 15) * 8;
-    double ra[8], rb[8];
+    T ra[8], rb[8];
     auto load_tile = [&](int k0) {
         const int gm = m0 + a_row;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int gk = k0 + a_k0 + e;
-            ra[e] = (gm < g.M && gk < g.K) ? gA[(int64_t)gm * g.lda + gk] : 0.0;
+            ra[e] = (gm < g.M && gk < g.K) ? gA[(int64_t)gm * g.lda + gk] : (T)0;
         }
         const int gk = k0 + b_k;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int gn = n0 + b_c0 + e;
-            rb[e] = (gk < g.K && gn < g.N) ? gB[(int64_t)gk * g.ldb + gn] : 0.0;
+            rb[e] = (gk < g.K && gn < g.N) ? gB[(int64_t)gk * g.ldb + gn] : (T)0;
         }
     };
     auto store_tile = [&](int buf) {
@@ -95,7 +121,7 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
         if (kt + 1 < nk) load_tile((kt + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            double fa[4], fb[4];
+            T fa[4], fb[4];
 #pragma unroll
             for (int f = 0; f < 4; ++f) fa[f] = As[cur][kk + lk][wm * 64 + f * 16 + li];
 #pragma unroll
@@ -104,14 +130,14 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = MF::step(fa[i], fb[j], acc[i][j]);
         }
         if (kt + 1 < nk) store_tile(cur ^ 1);
         __syncthreads();
     }
 
-    // epilogue: accumulator register r of lane l holds row l/16 + 4r, column
-    // l % 16 of its 16 x 16 block
+    // epilogue: accumulator register r of lane l holds column l % 16 and row
+    // MF::row(l / 16, r) of its 16 x 16 block
     double ssq = 0.0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -120,13 +146,13 @@ __device__ __forceinline__ void gemm_tile(const GemmArgs &g, int b, int part) {
             const int col = n0 + wn * 64 + j * 16 + li;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 64 + i * 16 + lk + 4 * r;
+                const int row = m0 + wm * 64 + i * 16 + MF::row(lk, r);
                 if (row < g.M && col < g.N) {
-                    double v = g.alpha * acc[i][j][r];
-                    if (g.beta != 0.0) v = fma(g.beta, glb(g.C)[(int64_t)row * g.ldc + col], v);
-                    if (row == col) v += g.gamma;
+                    T v = (T)g.alpha * acc[i][j][r];
+                    if (g.beta != 0.0) v = fma((T)g.beta, glb(g.C)[(int64_t)row * g.ldc + col], v);
+                    if (row == col) v += (T)g.gamma;
                     glb(g.D)[(int64_t)row * g.ldd + col] = v;
-                    ssq = fma(v, v, ssq);
+                    ssq = fma((double)v, (double)v, ssq);
                 }
             }
         }
@@ -147,7 +173,16 @@ gemm_f64_kernel(const GemmArgs g) {
     // XCD-aware renumbering: hardware workgroup b runs on XCD b % 8
     int b = blockIdx.x;
     if (ntiles % 8 == 0) b = (b % 8) * (ntiles / 8) + b / 8;
-    gemm_tile(g, b, blockIdx.x);
+    gemm_tile<double>(g, b, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(NTH, 2)
+gemm_f32_kernel(const GemmArgsT<float> g) {
+    if (g.run_flag && *g.run_flag == 0) return;
+    const int ntiles = ((g.M + BM - 1) / BM) * ((g.N + BN - 1) / BN);
+    int b = blockIdx.x;
+    if (ntiles % 8 == 0) b = (b % 8) * (ntiles / 8) + b / 8;
+    gemm_tile<float>(g, b, blockIdx.x);
 }
 
 // Many independent products in one launch: workgroup -> (problem, tile).
@@ -156,7 +191,7 @@ gemm_f64_grouped_kernel(const GemmArgs *__restrict__ probs, const int2 *__restri
     const int2 pt = tilemap[blockIdx.x];
     const GemmArgs g = probs[pt.x];
     if (g.run_flag && *g.run_flag == 0) return;
-    gemm_tile(g, pt.y, pt.y);
+    gemm_tile<double>(g, pt.y, pt.y);
 }
 
 }  // namespace
@@ -174,6 +209,13 @@ hipError_t launch_gemm_f64(const GemmArgs &g, hipStream_t s) {
     const int tiles = gemm_tiles(g.M, g.N);
     if (tiles == 0) return hipSuccess;
     hipLaunchKernelGGL(gemm_f64_kernel, dim3(tiles), dim3(NTH), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32(const GemmArgsT<float> &g, hipStream_t s) {
+    const int tiles = gemm_tiles(g.M, g.N);
+    if (tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(gemm_f32_kernel, dim3(tiles), dim3(NTH), 0, s, g);
     return hipGetLastError();
 }
 

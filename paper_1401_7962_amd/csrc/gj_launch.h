@@ -57,22 +57,26 @@ hipError_t launch_blk_finish(const BigHdr *hdr, const StepRec *steps, int n, int
                              int32_t *rowinv, int32_t *colinv, const double *W, int64_t ldw,
                              double *X, int64_t ldx, hipStream_t s);
 
-struct GemmArgs {
+template <typename T>
+struct GemmArgsT {
     int M, N, K;
-    const double *A;
+    const T *A;
     int64_t lda;
-    const double *B;
+    const T *B;
     int64_t ldb;
-    const double *C;
+    const T *C;
     int64_t ldc;
-    double *D;
+    T *D;
     int64_t ldd;
     double alpha, beta, gamma;
     double *norm_partials;
     const int32_t *run_flag;
 };
+using GemmArgs = GemmArgsT<double>;
 int gemm_tiles(int M, int N);
 hipError_t launch_gemm_f64(const GemmArgs &g, hipStream_t s);
+// the same product in FP32 (v_mfma_f32_16x16x4f32; FP32 accumulation)
+hipError_t launch_gemm_f32(const GemmArgsT<float> &g, hipStream_t s);
 // grouped: workgroup b computes tile tilemap[b].y of problem probs[tilemap[b].x]
 // (norm partial slot = tile index within the problem)
 hipError_t launch_gemm_f64_grouped(const GemmArgs *probs, const int2 *tilemap, int ntiles,

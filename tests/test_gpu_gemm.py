@@ -40,3 +40,31 @@ def test_dgemm_in_place(gj):
                 alpha=-1.0, beta=1.0)
     torch.cuda.synchronize()
     assert np.allclose(Cd.cpu().numpy(), C - A @ B, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (128, 128, 16), (1, 1, 1), (37, 91, 53),
+                                   (300, 200, 129), (512, 512, 512)])
+def test_sgemm_shapes(gj, M, N, K):
+    """The FP32 product (FP32 accumulation) against an FP64 NumPy product of
+    the same FP32 operands, with the bound of FP32 summation in any order:
+    it also pins the FP32 accumulator's lane layout (a wrong row map moves
+    whole rows of the 16 x 16 blocks)."""
+    import torch
+    rng = inputs.rng_for(0, 7200 + M + N + K)
+    A, B, C = (rng.standard_normal(s).astype(np.float32) for s in ((M, K), (K, N), (M, N)))
+    for alpha, beta, gamma in ((1.0, 0.0, 0.0), (-1.0, 0.0, 1.0), (-1.0, 1.0, 2.0)):
+        Ad, Bd, Cd = (torch.from_numpy(x).to("cuda") for x in (A, B, C))
+        D = gj.gj_sgemm(Ad, Bd, Cd, alpha=alpha, beta=beta, gamma=gamma)
+        torch.cuda.synchronize()
+        A64, B64, C64 = A.astype(np.float64), B.astype(np.float64), C.astype(np.float64)
+        want = alpha * (A64 @ B64) + beta * C64 + gamma * np.eye(M, N)
+        u = 2.0 ** -24
+        bound = (K + 4) * u * (np.abs(A64) @ np.abs(B64)) + 4 * u * (np.abs(C64) + np.abs(want)) + 1e-30
+        assert np.all(np.abs(D.cpu().numpy().astype(np.float64) - want) <= bound), (alpha, beta, gamma)
+
+
+def test_sgemm_rejects_wrong_dtype(gj):
+    import torch
+    A = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(gj.GJError):
+        gj.gj_sgemm(A, A)
