@@ -108,19 +108,23 @@ enum {
                                  residual stalls at about n u cond(A); these bring the forward
                                  error of X to about u.  gj_result.refine_iters counts all
                                  updates kept.  The workspace grows by 6 n^2 doubles. */
-    GJ_FLAG_BLOCKED = 16      /* gj_invert, GJ_PREC_FP64 with the full search only (else
-                                 GJ_E_INVALID_ARG; gj_det, gj_solve, gj_invert_batched:
-                                 GJ_E_UNSUPPORTED): delayed updates.  Each step eliminates on the
-                                 trailing block of rows and columns not yet pivoted (all that the
-                                 full search of Obs. 2-3 reads); every 256 steps the other rows
-                                 and columns receive those steps' eqs. 14-15 at once as FP64
-                                 matrix-core products (the theorem of section 1: the left
-                                 factors of the elimination may be grouped).  Pivots, rank,
-                                 result code and determinant are bit-identical to the unblocked
-                                 elimination; the inverse agrees up to rounding (the products
-                                 sum in another order), not bit for bit.  Orders up to 128 run
-                                 the on-chip kernel as without the flag.  The workspace holds two
-                                 n x (n + padding) arrays.  step_events are not recorded. */
+    GJ_FLAG_BLOCKED = 16      /* gj_invert with the full search only (else GJ_E_INVALID_ARG;
+                                 gj_det, gj_solve, gj_invert_batched: GJ_E_UNSUPPORTED): delayed
+                                 updates.  Each step eliminates on the trailing block of rows and
+                                 columns not yet pivoted (all that the full search of Obs. 2-3
+                                 reads); every 256 steps the other rows and columns receive those
+                                 steps' eqs. 14-15 at once as matrix-core products (the theorem
+                                 of section 1: the left factors of the elimination may be
+                                 grouped).  GJ_PREC_FP64: pivots, rank, result code and
+                                 determinant are bit-identical to the unblocked elimination; the
+                                 inverse agrees up to rounding (the products sum in another
+                                 order), not bit for bit.  GJ_PREC_FP32_REFINED: the FP32 stage
+                                 runs this way (FP32 products), with the unblocked FP32 stage's
+                                 pivots; refinement, fallback and determinant follow as without
+                                 the flag.  Orders up to 128 run the on-chip kernel as without
+                                 the flag.  The workspace holds two n x (n + padding) arrays of
+                                 the elimination's precision.  step_events (FP64) are not
+                                 recorded. */
 };
 
 /* gj_workspace_size op codes */

@@ -28,7 +28,7 @@ GJ_FLAG_REUSE_PLAN = 1
 GJ_FLAG_PIVOT_PARTIAL = 2   # partial pivoting on |a| (row swaps only)
 GJ_FLAG_PIVOT_PROGRAM = 4   # the section-3 program's rule: largest positive value in column k
 GJ_FLAG_ACCURATE = 8   # refined path: extra updates with error-free split residuals
-GJ_FLAG_BLOCKED = 16   # FP64: delayed updates (trailing-block steps, matrix-core products per panel)
+GJ_FLAG_BLOCKED = 16   # delayed updates (trailing-block steps, matrix-core products per panel); FP64 or the refined path's FP32 stage
 GJ_OP_INVERT, GJ_OP_DET, GJ_OP_INVERT_BATCHED, GJ_OP_SOLVE = 0, 1, 2, 3
 
 

@@ -43,8 +43,7 @@ bool read_opts(const gj_opts *o, Opts &out) {
                      GJ_FLAG_BLOCKED))
         return false;
     if ((o->flags & GJ_FLAG_ACCURATE) && o->precision != GJ_PREC_FP32_REFINED) return false;
-    if ((o->flags & GJ_FLAG_BLOCKED) &&
-        (o->precision != GJ_PREC_FP64 || (o->flags & (GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM))))
+    if ((o->flags & GJ_FLAG_BLOCKED) && (o->flags & (GJ_FLAG_PIVOT_PARTIAL | GJ_FLAG_PIVOT_PROGRAM)))
         return false;
     if ((o->flags & GJ_FLAG_PIVOT_PARTIAL) && (o->flags & GJ_FLAG_PIVOT_PROGRAM)) return false;
     if (std::isnan(o->zero_tol)) return false;
@@ -368,7 +367,7 @@ bool overlaps(const void *a, size_t an, const void *b, size_t bn) {
 
 size_t resid_ws(int n);
 struct RefinedLayout;
-size_t refined_ws(int n, bool acc);
+size_t refined_ws(int n, bool acc, bool blocked = false);
 
 // ------------------------------------------------ blocked elimination
 // Panels of kBlkNb steps on the trailing block, then the delayed updates as
@@ -389,11 +388,11 @@ constexpr int kBlkNb = 256;
 // with 256-step panels: m / 256 108.0 / 715.1, m / 128 128.7 / 739.1, the
 // table's rows above m = 2048 (m / 256 below) 107.5 / 713.3.
 constexpr int kBlkRowDiv = 256;
-BigShape blk_shape(int m) {
+BigShape blk_shape(int m, bool fp32) {
     const int div = env_int("GJ_BLK_RDIV", kBlkRowDiv);   // experiments
     int rows = 1;
     while (rows * 2 <= m / std::max(div, 1)) rows *= 2;
-    return big_shape(m, false, big_threads(m, false), 0, env_int("GJ_BIG_ROWS", 0) > 0 ? 0 : rows);
+    return big_shape(m, fp32, big_threads(m, fp32), 0, env_int("GJ_BIG_ROWS", 0) > 0 ? 0 : rows);
 }
 
 struct BlkLayout {
@@ -403,7 +402,9 @@ struct BlkLayout {
     size_t W2, tA, tB, perm, end;
 };
 
-BlkLayout blk_layout(int n) {
+// base: the layout's first byte (the refined path places it after its own
+// control block); an FP32 layout holds FP32 arrays.
+BlkLayout blk_layout(int n, bool fp32 = false, size_t base = 0) {
     BlkLayout L;
     int nb = env_int("GJ_BLK_NB", kBlkNb);   // panel width (experiments)
     L.nb = std::max(2, std::min(nb, 1024)) & ~1;   // even: block starts stay 16-byte aligned
@@ -411,34 +412,61 @@ BlkLayout blk_layout(int n) {
     int nblk = 1;
     for (int k0 = 0; k0 < n; k0 += L.nb) {
         const int m = n - k0;
-        const BigShape s = blk_shape(m);
+        const BigShape s = blk_shape(m, fp32);
         ldw = std::max<int64_t>(ldw, k0 + s.ldw);
         nblk = std::max(nblk, s.nblk);
     }
     L.ldw = (ldw + 15) / 16 * 16;
     L.nblk = nblk;
-    BigShape s0 = big_shape(n, false, big_threads(n, false));
+    BigShape s0 = big_shape(n, fp32, big_threads(n, fp32));
     s0.ldw = L.ldw;
     s0.nblk = nblk;
-    L.bb = big_bufs(s0, false, 0);
+    L.bb = big_bufs(s0, fp32, base);
+    const size_t es = fp32 ? 4 : 8;
     size_t c = L.bb.end;
-    L.W2 = c; c = a256(c + (size_t)n * L.ldw * 8);
-    L.tA = c; c = a256(c + (size_t)n * L.nb * 8);     // k0 x nb, ld nb
-    L.tB = c; c = a256(c + (size_t)n * L.nb * 8);     // nb x k0, ld n
+    L.W2 = c; c = a256(c + (size_t)n * L.ldw * es);
+    L.tA = c; c = a256(c + (size_t)n * L.nb * es);    // k0 x nb, ld nb
+    L.tB = c; c = a256(c + (size_t)n * L.nb * es);    // nb x k0, ld n
     L.perm = c; c = a256(c + (size_t)6 * n * 4);      // prow[2], pcol[2], rowinv, colinv
     L.end = c;
     return L;
 }
 
-gj_status run_blocked(int n, const double *A, int64_t lda, double *X, int64_t ldx, int32_t *ipiv,
-                      int32_t *jpiv, gj_result *res, const Opts &o, void *ws, size_t ws_bytes,
-                      hipStream_t s) {
-    const BlkLayout L = blk_layout(n);
+// One product of the panel's delayed update, in the elimination's precision.
+hipError_t blk_gemm(bool fp32, int M, int N, int K, double alpha, const void *A, int64_t lda,
+                    const void *B, int64_t ldb, double beta, const void *C, int64_t ldc, void *D,
+                    int64_t ldd, hipStream_t s) {
+    if (fp32) {
+        GemmArgsT<float> g;
+        std::memset(&g, 0, sizeof(g));
+        g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.beta = beta;
+        g.A = (const float *)A; g.lda = lda; g.B = (const float *)B; g.ldb = ldb;
+        g.C = (const float *)C; g.ldc = ldc; g.D = (float *)D; g.ldd = ldd;
+        return launch_gemm_f32(g, s);
+    }
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.M = M; g.N = N; g.K = K; g.alpha = alpha; g.beta = beta;
+    g.A = (const double *)A; g.lda = lda; g.B = (const double *)B; g.ldb = ldb;
+    g.C = (const double *)C; g.ldc = ldc; g.D = (double *)D; g.ldd = ldd;
+    return launch_gemm_f64(g, s);
+}
+
+// fp32: the first stage of the refined path (zero threshold 0, as its
+// unblocked FP32 elimination); X may be null (no gather).  rows / cols, when
+// given, receive the device addresses of the final pivot-order maps
+// (position -> original row / column).
+gj_status run_blocked(bool fp32, int n, const double *A, int64_t lda, double *X, int64_t ldx,
+                      int32_t *ipiv, int32_t *jpiv, gj_result *res, double zero_tol,
+                      double eps_default, void *ws, size_t ws_bytes, size_t base, hipStream_t s,
+                      const int32_t **rows = nullptr, const int32_t **cols = nullptr) {
+    const BlkLayout L = blk_layout(n, fp32, base);
     if (ws_bytes < L.end) return GJ_E_WORKSPACE;
     char *w = (char *)ws;
     const int64_t ldw = L.ldw;
-    double *Wb[2] = {reinterpret_cast<double *>(w + L.bb.W), reinterpret_cast<double *>(w + L.W2)};
-    double *tA = reinterpret_cast<double *>(w + L.tA), *tB = reinterpret_cast<double *>(w + L.tB);
+    const size_t es = fp32 ? 4 : 8;
+    char *Wb[2] = {w + L.bb.W, w + L.W2};
+    char *tA = w + L.tA, *tB = w + L.tB;
     int32_t *perm = reinterpret_cast<int32_t *>(w + L.perm);
     int32_t *prow[2] = {perm, perm + n}, *pcol[2] = {perm + 2 * n, perm + 3 * n};
     int32_t *rowinv = perm + 4 * n, *colinv = perm + 5 * n;
@@ -447,25 +475,26 @@ gj_status run_blocked(int n, const double *A, int64_t lda, double *X, int64_t ld
     hipError_t e = launch_blk_init_perm(prow[0], pcol[0], n, s);
     if (e != hipSuccess) return hip_fail(e);
     int cur = 0;
+    auto at = [&](char *base_, int64_t row, int64_t col) { return base_ + (row * ldw + col) * (int64_t)es; };
     for (int k0 = 0; k0 < n; k0 += L.nb) {
         const int m = n - k0, nbp = std::min(L.nb, m);
-        const BigShape sh = blk_shape(m);
+        const BigShape sh = blk_shape(m, fp32);
         const int nt = sh.nt;
         // the block's row shape and candidate list fit the layout
         if (k0 + sh.ldw > ldw || sh.nblk > L.nblk) return GJ_E_WORKSPACE;
         BigDesc d = make_desc(sh, L.bb, w, A, lda, X, ldx, ipiv, jpiv, res);
-        d.W = Wb[cur] + (int64_t)k0 * ldw + k0;
+        d.W = at(Wb[cur], k0, k0);
         d.ldw = ldw;
         d.mstride = ldw;
         d.steps = steps + k0;
         d.k0 = k0;
         d.inplace = k0 > 0;
         // nbp steps on the trailing block, no finish
-        e = launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false),
+        e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32),
                        big_counted(sh), false, 0, nullptr, nullptr, d, nullptr, sh.nblk, 0, nbp, 0,
-                       o.zero_tol, kEps64, 0, nullptr, nullptr, s);
+                       zero_tol, eps_default, 0, nullptr, nullptr, s);
         if (e != hipSuccess) return hip_fail(e);
-        e = launch_blk_panel_end(hdr, d.rowlog + (size_t)(nbp & 1) * ldw,
+        e = launch_blk_panel_end(fp32, hdr, d.rowlog + (size_t)(nbp & 1) * ldw,
                                  d.collog + (size_t)(nbp & 1) * ldw, m, d.rowphys, d.colphys,
                                  steps + k0, nbp, k0, Wb[cur], Wb[cur ^ 1], ldw, n, tA, L.nb, tB,
                                  n, prow[cur], pcol[cur], prow[cur ^ 1], pcol[cur ^ 1], s);
@@ -474,42 +503,26 @@ gj_status run_blocked(int n, const double *A, int64_t lda, double *X, int64_t ld
         if (k0 == 0) continue;
         // the panel's steps on the other rows and columns (b: the panel's
         // pivots, 1: the k0 earlier ones, 3: the rest)
-        double *Wc = Wb[cur];
-        GemmArgs g;
-        std::memset(&g, 0, sizeof(g));
-        g.alpha = 1.0;
+        char *Wc = Wb[cur];
         // W_b1 = T W_b1(old)
-        g.M = nbp; g.N = k0; g.K = nbp;
-        g.A = Wc + (int64_t)k0 * ldw + k0; g.lda = ldw;
-        g.B = tB; g.ldb = n;
-        g.D = Wc + (int64_t)k0 * ldw; g.ldd = ldw;
-        e = launch_gemm_f64(g, s);
+        e = blk_gemm(fp32, nbp, k0, nbp, 1.0, at(Wc, k0, k0), ldw, tB, n, 0.0, nullptr, 0,
+                     at(Wc, k0, 0), ldw, s);
         if (e != hipSuccess) return hip_fail(e);
         // W_31 += W_3b W_b1(old), W_3b = -W_3b(old) T from the panel
         if (m > nbp) {
-            g.M = m - nbp; g.N = k0; g.K = nbp;
-            g.A = Wc + (int64_t)(k0 + nbp) * ldw + k0; g.lda = ldw;
-            g.B = tB; g.ldb = n;
-            g.C = Wc + (int64_t)(k0 + nbp) * ldw; g.ldc = ldw;
-            g.D = Wc + (int64_t)(k0 + nbp) * ldw; g.ldd = ldw;
-            g.beta = 1.0;
-            e = launch_gemm_f64(g, s);
+            e = blk_gemm(fp32, m - nbp, k0, nbp, 1.0, at(Wc, k0 + nbp, k0), ldw, tB, n, 1.0,
+                         at(Wc, k0 + nbp, 0), ldw, at(Wc, k0 + nbp, 0), ldw, s);
             if (e != hipSuccess) return hip_fail(e);
         }
         // W_1* -= W_1b(old) W_b* (W_1b zeroed by the copy: it becomes -W_1b(old) T)
-        g.M = k0; g.N = n; g.K = nbp;
-        g.A = tA; g.lda = L.nb;
-        g.B = Wc + (int64_t)k0 * ldw; g.ldb = ldw;
-        g.C = Wc; g.ldc = ldw;
-        g.D = Wc; g.ldd = ldw;
-        g.alpha = -1.0;
-        g.beta = 1.0;
-        e = launch_gemm_f64(g, s);
+        e = blk_gemm(fp32, k0, n, nbp, -1.0, tA, L.nb, at(Wc, k0, 0), ldw, 1.0, Wc, ldw, Wc, ldw, s);
         if (e != hipSuccess) return hip_fail(e);
     }
-    e = launch_blk_finish(hdr, steps, n, ipiv, jpiv, res, prow[cur], pcol[cur], rowinv, colinv,
+    e = launch_blk_finish(fp32, hdr, steps, n, ipiv, jpiv, res, prow[cur], pcol[cur], rowinv, colinv,
                           Wb[cur], ldw, X, ldx, s);
     if (e != hipSuccess) return hip_fail(e);
+    if (rows) *rows = prow[cur];
+    if (cols) *cols = pcol[cur];
     return GJ_OK;
 }
 
@@ -519,7 +532,7 @@ bool use_blocked(int n, const Opts &o, bool det_only) {
 
 size_t single_ws(int n, const Opts &o, bool det_only) {
     if (o.precision == GJ_PREC_FP32_REFINED)
-        return refined_ws(n, (o.flags & GJ_FLAG_ACCURATE) && !det_only);
+        return refined_ws(n, (o.flags & GJ_FLAG_ACCURATE) && !det_only, use_blocked(n, o, det_only));
     size_t need = 256;
     if (use_blocked(n, o, det_only)) {
         need = blk_layout(n).end;
@@ -640,13 +653,15 @@ struct RefinedLayout {
     int nparts;
 };
 
-RefinedLayout refined_layout(int n, bool acc = false) {
+RefinedLayout refined_layout(int n, bool acc = false, bool blocked = false) {
     RefinedLayout L;
     size_t c = 0;
     const size_t n2 = (size_t)n * n * 8;
     L.ctl = c; c = a256(c + refine_ctl_bytes());
     L.big32 = c;
-    if (n > kOnchipMax) {
+    if (n > kOnchipMax && blocked) {
+        c = blk_layout(n, true, c).end;             // FP32 elimination with delayed updates
+    } else if (n > kOnchipMax) {
         BigShape s = big_shape(n, true, big_threads(n, true));
         c = big_bufs(s, true, c).end;
     }
@@ -685,7 +700,8 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
                              int32_t *ipiv, int32_t *jpiv, gj_result *res, const Opts &o, char *w,
                              hipStream_t s, bool det_only) {
     const bool acc = (o.flags & GJ_FLAG_ACCURATE) && !det_only;
-    const RefinedLayout L = refined_layout(n, acc);
+    const bool blk = use_blocked(n, o, det_only);
+    const RefinedLayout L = refined_layout(n, acc, blk);
     void *ctl = w + L.ctl;
     double *Xw = reinterpret_cast<double *>(w + L.xw);
     double *R = reinterpret_cast<double *>(w + L.r);
@@ -704,7 +720,16 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
     // 1. FP32 elimination (zero threshold 0): X0 in X, pivots, FP32 status
     BigDesc d32;
     std::memset(&d32, 0, sizeof(d32));
-    if (n <= kOnchipMax) {
+    const int32_t *blk_rows = nullptr, *blk_cols = nullptr;
+    if (blk) {
+        // with delayed updates (FP32 products); the pivots are the unblocked
+        // FP32 elimination's, and the pivot-order maps come out of it
+        if (o.events && o.events[0]) GJ_TRY(hipEventRecord((hipEvent_t)o.events[0], s));
+        const gj_status bs = run_blocked(true, n, A, lda, X, ldx, ipiv, jpiv, res, 0.0, 0.0, w, L.end,
+                                         L.big32, s, &blk_rows, &blk_cols);
+        if (bs != GJ_OK) return bs;
+        if (o.events && o.events[1]) GJ_TRY(hipEventRecord((hipEvent_t)o.events[1], s));
+    } else if (n <= kOnchipMax) {
         MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0, nullptr};
         if (o.events && o.events[0]) GJ_TRY(hipEventRecord((hipEvent_t)o.events[0], s));
         GJ_TRY(launch_onchip(true, nullptr, nullptr, 0, nullptr, md, 1, A, det_only ? nullptr : X,
@@ -727,7 +752,9 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
     std::memset(&m, 0, sizeof(m));
     m.A = A; m.lda = lda; m.X = X; m.ldx = ldx; m.Xw = Xw; m.B = R;
     m.ipiv = ipiv; m.jpiv = jpiv;
-    if (n <= kOnchipMax) {
+    if (blk) {
+        m.rows = blk_rows; m.cols = blk_cols;
+    } else if (n <= kOnchipMax) {
         m.rows = rows; m.cols = cols; m.rows_buf = rows; m.cols_buf = cols;
     } else {
         m.rows = d32.rowphys; m.cols = d32.colphys;
@@ -1335,7 +1362,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     return GJ_OK;
 }
 
-size_t refined_ws(int n, bool acc) { return refined_layout(n, acc).end; }
+size_t refined_ws(int n, bool acc, bool blocked) { return refined_layout(n, acc, blocked).end; }
 
 // Residual of a plain FP64 result (want_resid): needs n^2 + partial sums.
 size_t resid_ws(int n) {
@@ -1575,7 +1602,8 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
         if (o.precision == GJ_PREC_FP32_REFINED)
             return run_refined_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, (char *)ws, s, false);
         const bool blocked = use_blocked(n, o, false);
-        gj_status st = blocked ? run_blocked(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes, s)
+        gj_status st = blocked ? run_blocked(false, n, A, lda, X, ldx, ipiv, jpiv, res, o.zero_tol, kEps64,
+                                             ws, ws_bytes, 0, s)
                                : run_single(n, A, lda, X, ldx, ipiv, jpiv, res, o, ws, ws_bytes, s, false);
         if (st != GJ_OK || !o.want_resid) return st;
         size_t off = 0;

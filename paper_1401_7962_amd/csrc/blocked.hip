@@ -1,4 +1,5 @@
-// blocked.hip -- full-pivot Gauss-Jordan with delayed updates (FP64).
+// blocked.hip -- full-pivot Gauss-Jordan with delayed updates (FP64, and
+// FP32 for the first stage of the refined path).
 //
 // Full pivoting only needs the trailing block S of the array: the rows and
 // columns not yet eliminated (after k steps of eqs. 14-15, S is the Schur
@@ -64,11 +65,12 @@ blk_panel_maps(const BigHdr *__restrict__ hdr, const int32_t *__restrict__ rl,
 // One workgroup per destination row r: W2(r, c) = W(src(r), src(c)), where
 // rows and columns before k0 stay and the block's follow rphys / cphys.
 // Columns from n to ldw are zeroed (the block's row shape may reach them).
+template <typename T>
 __global__ void __launch_bounds__(256)
-blk_permute(const BigHdr *__restrict__ hdr, const double *__restrict__ W, double *__restrict__ W2,
+blk_permute(const BigHdr *__restrict__ hdr, const T *__restrict__ W, T *__restrict__ W2,
             int64_t ldw, int n, int k0, int nbp, const int32_t *__restrict__ rphys,
             const int32_t *__restrict__ cphys, const StepRec *__restrict__ last,
-            double *__restrict__ tA, int ldta, double *__restrict__ tB, int64_t ldtb,
+            T *__restrict__ tA, int ldta, T *__restrict__ tB, int64_t ldtb,
             const int32_t *__restrict__ prow_old, const int32_t *__restrict__ pcol_old,
             int32_t *__restrict__ prow_new, int32_t *__restrict__ pcol_new) {
     if (hdr->status != 0) return;
@@ -77,20 +79,20 @@ blk_permute(const BigHdr *__restrict__ hdr, const double *__restrict__ W, double
     const StepRec ls = *last;
     const int lc = k0 + ls.cphys;
     const bool fix = sr == k0 + ls.rphys;   // the last pivot row: its eq. 14 on the block's columns
-    const double lp = ls.p;
-    const double *Ws = W + (int64_t)sr * ldw;
-    double *Wd = W2 + (int64_t)r * ldw;
+    const T lp = (T)ls.p;   // the pivot, exact in T (the elimination's own value)
+    const T *Ws = W + (int64_t)sr * ldw;
+    T *Wd = W2 + (int64_t)r * ldw;
     const bool in_b = r >= k0 && r < k0 + nbp;
     for (int c = t; c < ldw; c += 256) {
-        double x = 0.0;
+        T x = (T)0;
         if (c < n) {
             const int sc = c < k0 ? c : k0 + cphys[c - k0];
             x = Ws[sc];
-            if (fix && sc >= k0) x = ((sc == lc) ? 1.0 : x) / lp;
+            if (fix && sc >= k0) x = ((sc == lc) ? (T)1 : x) / lp;
             if (in_b && c < k0) tB[(int64_t)(r - k0) * ldtb + c] = x;
             if (r < k0 && c >= k0 && c < k0 + nbp) {
                 tA[(int64_t)r * ldta + (c - k0)] = x;
-                x = 0.0;
+                x = (T)0;
             }
         }
         Wd[c] = x;
@@ -156,8 +158,9 @@ blk_finish(const BigHdr *__restrict__ hdr, const StepRec *__restrict__ steps, in
 }
 
 // X(i, j) = W(colinv[i], rowinv[j]); NaN when the elimination stopped.
+template <typename T>
 __global__ void __launch_bounds__(256)
-blk_gather(const BigHdr *__restrict__ hdr, const double *__restrict__ W, int64_t ldw, int n,
+blk_gather(const BigHdr *__restrict__ hdr, const T *__restrict__ W, int64_t ldw, int n,
            const int32_t *__restrict__ rowinv, const int32_t *__restrict__ colinv,
            double *__restrict__ X, int64_t ldx) {
     const int status = hdr->status;
@@ -167,8 +170,8 @@ blk_gather(const BigHdr *__restrict__ hdr, const double *__restrict__ W, int64_t
             for (int j = threadIdx.x; j < n; j += 256) Xi[j] = __builtin_nan("");
             continue;
         }
-        const double *Ws = W + (int64_t)colinv[i] * ldw;
-        for (int j = threadIdx.x; j < n; j += 256) Xi[j] = Ws[rowinv[j]];
+        const T *Ws = W + (int64_t)colinv[i] * ldw;
+        for (int j = threadIdx.x; j < n; j += 256) Xi[j] = (double)Ws[rowinv[j]];
     }
 }
 
@@ -179,32 +182,43 @@ hipError_t launch_blk_init_perm(int32_t *prow, int32_t *pcol, int n, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_blk_panel_end(const BigHdr *hdr, const int32_t *rl, const int32_t *cl, int m,
-                                int32_t *rphys, int32_t *cphys, StepRec *steps_k0, int nbp, int k0,
-                                const double *W, double *W2, int64_t ldw, int n, double *tA,
-                                int ldta, double *tB, int64_t ldtb, const int32_t *prow_old,
+hipError_t launch_blk_panel_end(bool fp32, const BigHdr *hdr, const int32_t *rl, const int32_t *cl,
+                                int m, int32_t *rphys, int32_t *cphys, StepRec *steps_k0, int nbp,
+                                int k0, const void *W, void *W2, int64_t ldw, int n, void *tA,
+                                int ldta, void *tB, int64_t ldtb, const int32_t *prow_old,
                                 const int32_t *pcol_old, int32_t *prow_new, int32_t *pcol_new,
                                 hipStream_t s) {
     hipLaunchKernelGGL(blk_panel_maps, dim3((m + 255) / 256), dim3(256), 0, s, hdr, rl, cl, m, rphys,
                        cphys, steps_k0, nbp, k0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(blk_permute, dim3(n), dim3(256), 0, s, hdr, W, W2, ldw, n, k0, nbp, rphys,
-                       cphys, steps_k0 + (nbp - 1), tA, ldta, tB, ldtb, prow_old, pcol_old, prow_new,
-                       pcol_new);
+    if (fp32)
+        hipLaunchKernelGGL(blk_permute<float>, dim3(n), dim3(256), 0, s, hdr, (const float *)W,
+                           (float *)W2, ldw, n, k0, nbp, rphys, cphys, steps_k0 + (nbp - 1),
+                           (float *)tA, ldta, (float *)tB, ldtb, prow_old, pcol_old, prow_new,
+                           pcol_new);
+    else
+        hipLaunchKernelGGL(blk_permute<double>, dim3(n), dim3(256), 0, s, hdr, (const double *)W,
+                           (double *)W2, ldw, n, k0, nbp, rphys, cphys, steps_k0 + (nbp - 1),
+                           (double *)tA, ldta, (double *)tB, ldtb, prow_old, pcol_old, prow_new,
+                           pcol_new);
     return hipGetLastError();
 }
 
-hipError_t launch_blk_finish(const BigHdr *hdr, const StepRec *steps, int n, int32_t *ipiv,
-                             int32_t *jpiv, gj_result *res, const int32_t *prow, const int32_t *pcol,
-                             int32_t *rowinv, int32_t *colinv, const double *W, int64_t ldw,
-                             double *X, int64_t ldx, hipStream_t s) {
+hipError_t launch_blk_finish(bool fp32, const BigHdr *hdr, const StepRec *steps, int n,
+                             int32_t *ipiv, int32_t *jpiv, gj_result *res, const int32_t *prow,
+                             const int32_t *pcol, int32_t *rowinv, int32_t *colinv, const void *W,
+                             int64_t ldw, double *X, int64_t ldx, hipStream_t s) {
     hipLaunchKernelGGL(blk_finish, dim3((n + 255) / 256), dim3(256), 0, s, hdr, steps, n, ipiv, jpiv,
                        res, prow, pcol, rowinv, colinv);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(blk_gather, dim3(std::min(n, 4096)), dim3(256), 0, s, hdr, W, ldw, n, rowinv,
-                       colinv, X, ldx);
+    if (e != hipSuccess || !X) return e;
+    if (fp32)
+        hipLaunchKernelGGL(blk_gather<float>, dim3(std::min(n, 4096)), dim3(256), 0, s, hdr,
+                           (const float *)W, ldw, n, rowinv, colinv, X, ldx);
+    else
+        hipLaunchKernelGGL(blk_gather<double>, dim3(std::min(n, 4096)), dim3(256), 0, s, hdr,
+                           (const double *)W, ldw, n, rowinv, colinv, X, ldx);
     return hipGetLastError();
 }
 

@@ -46,16 +46,17 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted,
 
 // blocked elimination (blocked.hip)
 hipError_t launch_blk_init_perm(int32_t *prow, int32_t *pcol, int n, hipStream_t s);
-hipError_t launch_blk_panel_end(const BigHdr *hdr, const int32_t *rl, const int32_t *cl, int m,
-                                int32_t *rphys, int32_t *cphys, StepRec *steps_k0, int nbp, int k0,
-                                const double *W, double *W2, int64_t ldw, int n, double *tA,
-                                int ldta, double *tB, int64_t ldtb, const int32_t *prow_old,
+hipError_t launch_blk_panel_end(bool fp32, const BigHdr *hdr, const int32_t *rl, const int32_t *cl,
+                                int m, int32_t *rphys, int32_t *cphys, StepRec *steps_k0, int nbp,
+                                int k0, const void *W, void *W2, int64_t ldw, int n, void *tA,
+                                int ldta, void *tB, int64_t ldtb, const int32_t *prow_old,
                                 const int32_t *pcol_old, int32_t *prow_new, int32_t *pcol_new,
                                 hipStream_t s);
-hipError_t launch_blk_finish(const BigHdr *hdr, const StepRec *steps, int n, int32_t *ipiv,
-                             int32_t *jpiv, gj_result *res, const int32_t *prow, const int32_t *pcol,
-                             int32_t *rowinv, int32_t *colinv, const double *W, int64_t ldw,
-                             double *X, int64_t ldx, hipStream_t s);
+// X null: the record, pivots and position maps only
+hipError_t launch_blk_finish(bool fp32, const BigHdr *hdr, const StepRec *steps, int n,
+                             int32_t *ipiv, int32_t *jpiv, gj_result *res, const int32_t *prow,
+                             const int32_t *pcol, int32_t *rowinv, int32_t *colinv, const void *W,
+                             int64_t ldw, double *X, int64_t ldx, hipStream_t s);
 
 template <typename T>
 struct GemmArgsT {

@@ -107,8 +107,14 @@ def test_workspace_size(lib):
     assert gj.gj_workspace_size(gj.GJ_OP_DET, 500, None, blk) == 0
     assert gj.gj_workspace_size(gj.GJ_OP_SOLVE, 500, [2], blk) == 0
     assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 900], blk) == 0
-    assert gj.gj_workspace_size(gj.GJ_OP_INVERT, 500, None,
-                                gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_BLOCKED)) == 0
+    # the refined path's FP32 stage with delayed updates: two padded n x n FP32
+    # arrays in place of the streaming one, the refinement's buffers as before
+    rblk = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_BLOCKED)
+    assert (gj.gj_workspace_size(gj.GJ_OP_INVERT, 4096, None, rblk)
+            >= gj.gj_workspace_size(gj.GJ_OP_INVERT, 4096, None, ref) + 4096 * 4096 * 4)
+    assert (gj.gj_workspace_size(gj.GJ_OP_INVERT, 100, None, rblk)
+            == gj.gj_workspace_size(gj.GJ_OP_INVERT, 100, None, ref))
+    assert gj.gj_workspace_size(gj.GJ_OP_INVERT_BATCHED, 2, [5, 900], rblk) == 0
 
 
 def test_argument_checks_without_gpu(lib):
@@ -121,9 +127,10 @@ def test_argument_checks_without_gpu(lib):
     o = gj.make_opts(flags=32)
     assert lib.gj_invert(4, fake, 4, P(1 << 24), 4, fake, fake, fake, ctypes.byref(o), None, 0,
                          None) == gj.GJ_E_INVALID_ARG
-    # delayed updates: FP64 full search only; not for the determinant, solve or batches
-    for bad in (gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=gj.GJ_FLAG_BLOCKED),
-                gj.make_opts(flags=gj.GJ_FLAG_BLOCKED | gj.GJ_FLAG_PIVOT_PARTIAL)):
+    # delayed updates: full search only; not for the determinant, solve or batches
+    for bad in (gj.make_opts(flags=gj.GJ_FLAG_BLOCKED | gj.GJ_FLAG_PIVOT_PARTIAL),
+                gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED,
+                             flags=gj.GJ_FLAG_BLOCKED | gj.GJ_FLAG_PIVOT_PROGRAM)):
         assert lib.gj_invert(4, fake, 4, P(1 << 24), 4, fake, fake, fake, ctypes.byref(bad), None, 0,
                              None) == gj.GJ_E_INVALID_ARG
     blk = gj.make_opts(flags=gj.GJ_FLAG_BLOCKED)

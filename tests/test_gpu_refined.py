@@ -253,3 +253,48 @@ def test_refined_batched_mixed(gj):
         lu = oracle.lu_static_det_f64(A, i32, j32)
         assert r["det_sign"] == lu["det_sign"], where
         assert abs(r["logabsdet"] - lu["logabsdet"]) <= 1e-11 * max(1.0, abs(lu["logabsdet"])), where
+
+
+@pytest.mark.parametrize("n,cond,nb", [(300, 1e4, 64), (333, 1e8, 128), (777, 1e6, 96),
+                                       (1000, 1e2, 256)])
+def test_refined_blocked(gj, n, cond, nb, monkeypatch):
+    """GJ_FLAG_BLOCKED on the refined path: the FP32 stage eliminates with
+    delayed updates (FP32 matrix-core products between panels), which leaves
+    the trailing block's values, so the pivot sequence is the FP32 oracle's
+    bit for bit; the refined inverse and determinant are held to the same bars
+    as the unblocked refined path."""
+    monkeypatch.setenv("GJ_BLK_NB", str(nb))
+    A = inputs.conditioned(n, cond, inputs.rng_for(0, 6500 + n))
+    X, ipiv, jpiv, r = _refined(gj, A, flags=gj.GJ_FLAG_BLOCKED)
+    assert r["code"] == 0, r
+    X32, i32, j32, _ = oracle.gj_invert_f32(A.astype(np.float32))
+    assert np.array_equal(ipiv, i32) and np.array_equal(jpiv, j32)
+    Xo, _, _, _ = oracle.gj_invert_f64(A)
+    if cond <= 1e4:
+        assert _rel(X, Xo) <= 1e-12
+    if n <= 520:
+        Xt, _, _, _ = oracle.gj_invert_f80(A)
+        assert _rel(X, Xt) <= 4 * _rel(Xo, Xt) + 1e-14
+    else:
+        Xt = oracle.inverse_truth(A, Xo)
+        assert _rel(X, Xt) <= 4 * _rel(Xo, Xt) + 1e-14
+    lu = oracle.lu_static_det_f64(A, i32, j32)
+    assert r["det_sign"] == lu["det_sign"] == 1
+    assert abs(r["logabsdet"] - lu["logabsdet"]) <= 1e-11 * abs(lu["logabsdet"])
+    # the same call without the flag: same pivots, refined X within rounding
+    X2, i2, j2, r2 = _refined(gj, A)
+    assert np.array_equal(i2, ipiv) and np.array_equal(j2, jpiv)
+    assert _rel(X, X2) <= 1e-12 if cond <= 1e4 else _rel(X, Xt) <= 4 * _rel(X2, Xt) + 1e-14
+
+
+def test_refined_blocked_singular(gj, monkeypatch):
+    """A rank-deficient input stops the FP32 stage inside a panel; the FP64
+    fallback then reports the oracle's rank and code."""
+    monkeypatch.setenv("GJ_BLK_NB", "64")
+    rng = inputs.rng_for(0, 6600)
+    n, rank = 300, 200
+    A = rng.standard_normal((n, rank)) @ rng.standard_normal((rank, n))
+    X, ipiv, jpiv, r = _refined(gj, A, flags=gj.GJ_FLAG_BLOCKED)
+    _, io, jo, ro = oracle.gj_invert_f64(A)
+    assert r["code"] == ro["code"] != 0 and r["rank"] == ro["rank"]
+    assert np.array_equal(ipiv, io) and np.array_equal(jpiv, jo)
