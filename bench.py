@@ -474,7 +474,11 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
     stream = torch.cuda.current_stream()
     for name, prec, flags in (("plain_fp64", gj.GJ_PREC_FP64, 0),
                               ("fp32_refined", gj.GJ_PREC_FP32_REFINED, 0),
-                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE)):
+                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE),
+                              ("plain_fp64_blocked", gj.GJ_PREC_FP64, gj.GJ_FLAG_BLOCKED),
+                              ("fp32_refined_blocked", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_BLOCKED)):
+        # the FP64 blocked elimination records no step events
+        timed_steps = not (flags & gj.GJ_FLAG_BLOCKED and prec == gj.GJ_PREC_FP64)
         opts = gj.make_opts(precision=prec, flags=flags)
         X = torch.empty_like(A)
         ip = torch.empty(n, dtype=torch.int32, device="cuda")
@@ -487,39 +491,54 @@ def bench_conditioned_8192(n: int = 8192, reps: int = 2):
         e = _events(4 * reps, stream)
         for k in range(reps):
             so = gj.make_opts(precision=prec, flags=flags,
-                              step_events=(ctypes_ptr(e[4 * k + 1]), ctypes_ptr(e[4 * k + 2])))
+                              step_events=(ctypes_ptr(e[4 * k + 1]), ctypes_ptr(e[4 * k + 2]))
+                              if timed_steps else (None, None))
             e[4 * k].record()
             gj.gj_invert(A, X, ip, jp, res, so, ws)
             e[4 * k + 3].record()
         torch.cuda.synchronize()
         best = min(range(reps), key=lambda k: e[4 * k].elapsed_time(e[4 * k + 3]))
         ms = e[4 * best].elapsed_time(e[4 * best + 3])
-        steps_ms = e[4 * best + 1].elapsed_time(e[4 * best + 2])
+        steps_ms = e[4 * best + 1].elapsed_time(e[4 * best + 2]) if timed_steps else None
         r = gj.results_to_dicts(res)[0]
         del ws
         R = gj.gj_dgemm(A, X, gamma=1.0, alpha=-1.0)
         resid = float(torch.linalg.norm(R) / (torch.linalg.norm(A) * torch.linalg.norm(X)))
         del R
-        # the elimination's step kernel: each launch reads and writes the
-        # whole n x n array once (16 n^2 B in FP64, 8 n^2 B in FP32)
         esz = 8 if prec == gj.GJ_PREC_FP64 else 4
-        gbs = 2.0 * esz * n * n * n / (steps_ms * 1e-3) / 1e9
         out[name] = {"ms": round(ms, 1), "inversions_per_s": round(1e3 / ms, 4), "code": r["code"],
                      "refine_iters": r["refine_iters"], "logabsdet": r["logabsdet"],
-                     "det_sign": r["det_sign"], "resid": resid,
-                     "elimination_ms": round(steps_ms, 1),
-                     "step_roofline": {"bound": "hbm", "kernel": "gj_big_step (%s)" % ("FP64" if esz == 8 else "FP32"),
-                                       "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                       "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                       "alg_bytes_per_launch": 2 * esz * n * n,
-                                       "per_launch_us": round(steps_ms * 1e3 / n, 2)}}
+                     "det_sign": r["det_sign"], "resid": resid}
+        if steps_ms is not None and not flags & gj.GJ_FLAG_BLOCKED:
+            # the elimination's step kernel: each launch reads and writes the
+            # whole n x n array once (16 n^2 B in FP64, 8 n^2 B in FP32)
+            gbs = 2.0 * esz * n * n * n / (steps_ms * 1e-3) / 1e9
+            out[name]["elimination_ms"] = round(steps_ms, 1)
+            out[name]["step_roofline"] = {
+                "bound": "hbm", "kernel": "gj_big_step (%s)" % ("FP64" if esz == 8 else "FP32"),
+                "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": 2 * esz * n * n,
+                "per_launch_us": round(steps_ms * 1e3 / n, 2)}
+        elif steps_ms is not None:
+            # delayed updates: the steps sweep only the trailing block (order
+            # n - k0 in the panel starting at k0); the products between panels
+            # are inside the same interval
+            nb = 256
+            sweep = sum(2.0 * esz * (n - (k // nb) * nb) ** 2 for k in range(n))
+            out[name]["elimination_ms"] = round(steps_ms, 1)
+            out[name]["elimination_sweep_gbs"] = round(sweep / (steps_ms * 1e-3) / 1e9, 1)
         Xs[name] = X
+        print(f"[conditioned_{n}] {name}: {ms:.1f} ms", file=sys.stderr, flush=True)
     d = float(torch.linalg.norm(Xs["fp32_refined"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"]))
     out["refined_vs_plain_rel_frobenius"] = d
     out["accurate_vs_refined_rel_frobenius"] = float(
         torch.linalg.norm(Xs["fp32_refined_accurate"] - Xs["fp32_refined"]) / torch.linalg.norm(Xs["fp32_refined"]))
     out["speedup_accurate_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined_accurate"]["ms"], 3)
     out["speedup_refined_over_plain"] = round(out["plain_fp64"]["ms"] / out["fp32_refined"]["ms"], 3)
+    out["speedup_refined_blocked_over_plain_blocked"] = round(
+        out["plain_fp64_blocked"]["ms"] / out["fp32_refined_blocked"]["ms"], 3)
+    out["refined_blocked_vs_plain_rel_frobenius"] = float(
+        torch.linalg.norm(Xs["fp32_refined_blocked"] - Xs["plain_fp64"]) / torch.linalg.norm(Xs["plain_fp64"]))
     # roofline of the refinement's dominant kernel: the Newton-Schulz product
     # X R (n x n x n, FP64 MFMA), timed alone with HIP events
     X, R = Xs["fp32_refined"], Xs["plain_fp64"]
@@ -768,7 +787,9 @@ def bench_accuracy_exact(n: int = 4096, span: int = 20, reps: int = 2):
     out = {"n": n, "cond": 2.0 ** span}
     for name, prec, flags in (("plain_fp64", gj.GJ_PREC_FP64, 0),
                               ("fp32_refined", gj.GJ_PREC_FP32_REFINED, 0),
-                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE)):
+                              ("fp32_refined_accurate", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_ACCURATE),
+                              ("plain_fp64_blocked", gj.GJ_PREC_FP64, gj.GJ_FLAG_BLOCKED),
+                              ("fp32_refined_blocked", gj.GJ_PREC_FP32_REFINED, gj.GJ_FLAG_BLOCKED)):
         o = gj.make_opts(precision=prec, flags=flags)
         X, ip, jp, res = gj.gj_invert(A, opts=o)
         torch.cuda.synchronize()
