@@ -718,18 +718,33 @@ gj_big_finish(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
             d.jpiv[x] = -1;
         }
     }
-    if (bm.y == 0 && t == 0) {
+    // eq. 13: the product runs on one thread in step order; the records pass
+    // through LDS in chunks, so that it does not wait on global memory at
+    // every step
+    if (bm.y == 0) {
         if (status == 0) {
+            constexpr int kChunk = 1024;
+            __shared__ T s_p[kChunk];
+            __shared__ int s_flip[kChunk];
             DetAcc<T> det;
             det.init();
-            for (int k = 0; k < n; ++k) {
-                const StepRec s = d.steps[k];
-                det.mul((T)s.p);
-                if (s.rlog != k) det.sign = -det.sign;
-                if (s.clog != k) det.sign = -det.sign;
+            for (int b0 = 0; b0 < n; b0 += kChunk) {
+                const int cnt = min(kChunk, n - b0);
+                for (int y = t; y < cnt; y += 256) {
+                    const StepRec s = d.steps[b0 + y];
+                    s_p[y] = (T)s.p;
+                    s_flip[y] = (s.rlog != b0 + y) ^ (s.clog != b0 + y);
+                }
+                __syncthreads();
+                if (t == 0)
+                    for (int y = 0; y < cnt; ++y) {
+                        det.mul(s_p[y]);
+                        if (s_flip[y]) det.sign = -det.sign;
+                    }
+                __syncthreads();
             }
-            write_result_ok(d.res, n, det);
-        } else {
+            if (t == 0) write_result_ok(d.res, n, det);
+        } else if (t == 0) {
             write_result_fail(d.res, status, rank);
         }
     }
