@@ -392,6 +392,11 @@ BigShape blk_shape(int m, bool fp32) {
     const int div = env_int("GJ_BLK_RDIV", kBlkRowDiv);   // experiments
     int rows = 1;
     while (rows * 2 <= m / std::max(div, 1)) rows *= 2;
+    // FP32 blocks above 6144 take the table's rows (whole-inversion tuning):
+    // refined 8192^2 with FP32 delayed updates 679.7 ms against 693.9 with
+    // m / 256 everywhere (402.5 / 409.9 ms for the FP32 stage; table rows
+    // above 4096: 686.9, above 7000: 687.2)
+    if (fp32 && m > 6144) rows = 0;
     return big_shape(m, fp32, big_threads(m, fp32), 0, env_int("GJ_BIG_ROWS", 0) > 0 ? 0 : rows);
 }
 

@@ -298,3 +298,24 @@ def test_refined_blocked_singular(gj, monkeypatch):
     _, io, jo, ro = oracle.gj_invert_f64(A)
     assert r["code"] == ro["code"] != 0 and r["rank"] == ro["rank"]
     assert np.array_equal(ipiv, io) and np.array_equal(jpiv, jo)
+
+
+def test_refined_blocked_large_order(gj):
+    """An order whose first panels take the tuned whole-inversion row shape
+    (FP32 blocks above 6144): the blocked FP32 stage keeps the unblocked FP32
+    stage's pivot sequence bit for bit, and both refined inverses agree to
+    1e-12 (the input is diagonally dominant, cond ~ 2)."""
+    import torch
+    n = 6400
+    A = torch.from_numpy(inputs.single_dominant(n, offset=77)).to("cuda")
+    out = {}
+    for name, flags in (("blocked", gj.GJ_FLAG_BLOCKED), ("unblocked", 0)):
+        X, ip, jp, res = gj.gj_invert(A, opts=gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED, flags=flags))
+        torch.cuda.synchronize()
+        out[name] = (X, ip.cpu().numpy(), jp.cpu().numpy(), gj.results_to_dicts(res)[0])
+    Xb, ib, jb, rb = out["blocked"]
+    Xu, iu, ju, ru = out["unblocked"]
+    assert rb["code"] == ru["code"] == 0
+    assert np.array_equal(ib, iu) and np.array_equal(jb, ju)
+    assert float(torch.linalg.norm(Xb - Xu) / torch.linalg.norm(Xu)) <= 1e-12
+    assert abs(rb["logabsdet"] - ru["logabsdet"]) <= 1e-11 * abs(ru["logabsdet"])
