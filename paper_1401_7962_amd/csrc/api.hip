@@ -206,6 +206,17 @@ bool big_full(const BigShape &s, bool fp32) {
     const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
     return (s.ncol + per - 1) / per == 8;
 }
+// The step kernel's chunk count for one matrix: 8 when its rows fill all 8
+// chunks; 4 when they fill exactly 4 (below 1024 threads; such a shape has no
+// counted units), so that no unused chunk is loaded or looped over; else 0
+// (the 8-chunk kernel with per-chunk tests).
+int big_full_chunks(const BigShape &s, bool fp32) {
+    const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
+    const int64_t ch = (s.ncol + per - 1) / per;
+    if (ch == 8) return 8;
+    if (ch == 4 && s.nt < 1024 && !big_counted(s)) return 4;
+    return 0;
+}
 
 // Byte layout of one matrix's streaming-path buffers, relative to `base`.
 struct BigBufs {
@@ -495,7 +506,7 @@ gj_status run_blocked(bool fp32, int n, const double *A, int64_t lda, double *X,
         d.k0 = k0;
         d.inplace = k0 > 0;
         // nbp steps on the trailing block, no finish
-        e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full(sh, fp32),
+        e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)), big_full_chunks(sh, fp32),
                        big_counted(sh), false, 0, nullptr, nullptr, d, nullptr, sh.nblk, 0, nbp, 0,
                        zero_tol, eps_default, 0, nullptr, nullptr, s);
         if (e != hipSuccess) return hip_fail(e);
@@ -585,7 +596,7 @@ gj_status run_solve(int n, int m, const double *A, int64_t lda, const double *B,
     d.B = B;
     d.ldb = ldb;
     d.rule = o.rule;
-    const bool full = o.rule == 0 && (rhs || big_full(sh, false));
+    const int full = (o.rule == 0 && (rhs || big_full(sh, false))) ? 8 : 0;
     hipError_t e = launch_big(false, sh.nt, big_nt_loads(big_swept_bytes(sh, false)),
                               full, o.rule == 0 && !rhs && big_counted(sh), rhs, o.rule, nullptr,
                               nullptr, d, nullptr, sh.nblk, sh.nblk, n, sh.nblk, o.zero_tol,
@@ -630,7 +641,7 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
     BigDesc d = make_desc(sh, bb, (char *)ws, A, lda, X, ldx, ipiv, jpiv, res);
     d.rule = o.rule;
     hipError_t e = launch_big(fp32, nt, big_nt_loads(big_swept_bytes(sh, fp32)),
-                              o.rule == 0 && big_full(sh, fp32), o.rule == 0 && big_counted(sh),
+                              o.rule == 0 ? big_full_chunks(sh, fp32) : 0, o.rule == 0 && big_counted(sh),
                               false, o.rule, nullptr, nullptr,
                               d, nullptr, sh.nblk, sh.nblk, n,
                               det_only ? 0 : sh.nblk, o.zero_tol, eps_default, det_only ? 1 : 0,
@@ -745,7 +756,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, true, nt);
         BigBufs bb = big_bufs(sh, true, L.big32);
         d32 = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full(sh, true), big_counted(sh), false, 0,
+        GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full_chunks(sh, true), big_counted(sh), false, 0,
                           nullptr, nullptr, d32,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, 0.0, 0.0, det_only ? 1 : 0, o.events, nullptr, s));
@@ -853,7 +864,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         BigShape sh = big_shape(n, false, nt);
         BigBufs bb = big_bufs(sh, false, L.over64);
         BigDesc d = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
-        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full(sh, false), big_counted(sh), false, 0,
+        GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full_chunks(sh, false), big_counted(sh), false, 0,
                           nullptr, nullptr, d,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
@@ -1312,7 +1323,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)E.bmap.size();
-        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full, E.big_counted, false, 0,
+        GJ_TRY(launch_big(true, E.big_nt, big_nt_loads(E.big_swept), E.big_full ? 8 : 0, E.big_counted, false, 0,
                           reinterpret_cast<const BigDesc *>(w + E.off_descs),
                           reinterpret_cast<const int2 *>(w + E.off_bmap), BigDesc(),
                           E.grid_per_step.data(), nb, nb, E.big_max_n, nb, 0.0, 0.0, 0, o.events,
@@ -1339,7 +1350,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     }
     if (!E.big_members.empty()) {
         const int nb = (int)P.fb_bmap.size();
-        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full, P.fb_counted, false, 0,
+        GJ_TRY(launch_big(false, P.fb_nt, big_nt_loads(P.fb_swept), P.fb_full ? 8 : 0, P.fb_counted, false, 0,
                           reinterpret_cast<const BigDesc *>(w + P.off_fb_descs),
                           reinterpret_cast<const int2 *>(w + P.off_fb_bmap), BigDesc(),
                           P.fb_grid.data(), nb, nb, E.big_max_n, nb, o.zero_tol, kEps64, 0, nullptr,
@@ -1796,7 +1807,7 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
         }
         if (!P.big_members.empty()) {
             const int nb = (int)P.bmap.size();
-            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full, P.big_counted, false, 0,
+            hipError_t e = launch_big(fp32, P.big_nt, big_nt_loads(P.big_swept), P.big_full ? 8 : 0, P.big_counted, false, 0,
                                       reinterpret_cast<const BigDesc *>(w + P.off_descs),
                                       reinterpret_cast<const int2 *>(w + P.off_bmap), BigDesc(),
                                       P.grid_per_step.data(), nb, nb, P.big_max_n, nb, o.zero_tol,

@@ -90,7 +90,10 @@ __device__ inline T vget(const VT &x, int e) { return reinterpret_cast<const T *
 template <typename VT, typename T>
 __device__ inline void vset(VT &x, int e, T v) { reinterpret_cast<T *>(&x)[e] = v; }
 
-constexpr int kNch = 8;  // column chunks per thread: n <= kNch * V * threads-per-row
+// Column chunks per thread of the step kernel (its NCH): n <= NCH * V * threads-per-row.
+// 8 in general; a shape whose rows fill exactly 4 chunks per thread gets a 4-chunk
+// kernel, whose loops and register arrays then hold no unused chunk.
+constexpr int kNch = 8;
 // Rows a thread holds in registers at once in the step kernel (their loads
 // are in flight together; the first group is requested before the candidate
 // reduction).  The 1024-thread workgroups have 128 VGPRs per lane: they load
@@ -247,16 +250,16 @@ gj_big_init(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 }
 
 // ------------------------------------------------------------------ step
-// FULL: every matrix of the launch uses all kNch chunks per thread (the
+// FULL: every matrix of the launch uses all NCH chunks per thread (the
 // chunk tests then fold away; they cost about 8% at n = 4096).
 // CNT: some units may come from the per-step counter.  Without it each
 // workgroup sweeps only its own rows, with no barrier in the sweep.
 // RULE: the pivot rule (d.rule); 1 and 2 restrict the candidates to the
 // next column, 2 scores the signed value.
-// RHS: a solve whose A fills all kNch chunks; B's m columns sit after them,
-// from column rhs0 = kNch * tpr * VE, as a partial extra chunk held by the
+// RHS: a solve whose A fills all NCH = 8 chunks; B's m columns sit after them,
+// from column rhs0 = 8 * tpr * VE, as a partial extra chunk held by the
 // first ceil(m / VE) threads of each row (FULL, 256/512 threads only).
-template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS, int RULE>
+template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS, int RULE, int NCH>
 __global__ void __launch_bounds__(NT)
 gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, const BigDesc single,
             int k, double zero_tol, double eps_default, int det_only,
@@ -283,7 +286,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const gptr<T> W = glb(reinterpret_cast<T *>(d.W));
     const int64_t ldw = d.ldw;
     static_assert(!RHS || (FULL && kEarlyRows<NT>), "the extra chunk needs the full register layout");
-    const int nch = RHS ? kNch : (d.ncol + tpr * VE - 1) / (tpr * VE);   // chunks holding A's (and B's) columns
+    const int nch = RHS ? NCH : (d.ncol + tpr * VE - 1) / (tpr * VE);   // chunks holding A's (and B's) columns
     const int nrc = RHS ? (d.ncol - d.rhs0 + VE - 1) / VE : 1;   // threads of a row holding B
     const int bcol = d.rhs0 + min(tc, nrc - 1) * VE;            // this thread's B columns (clamped)
     const bool bown = tc < nrc;
@@ -321,9 +324,9 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     const int dyn0 = d.nblk * S;                   // first unit of the counter
     const bool dyn = CNT && dyn0 < nunits;         // (then every workgroup has S units)
     const int ro_own = rl_old[nsr > 0 ? r0 + min(t, nsr - 1) : 0];   // old logical index of own row t
-    VI co[kNch];
+    VI co[NCH];
 #pragma unroll
-    for (int c = 0; c < kNch; ++c)   // in bounds: the maps hold ldw >= nch * tpr * VE entries
+    for (int c = 0; c < NCH; ++c)   // in bounds: the maps hold ldw >= nch * tpr * VE entries
         co[c] = *reinterpret_cast<gptr<const VI>>(cl_old + (c < nch ? c : 0) * tpr * VE + tc * VE);
 
     // ---- 1. reduce the candidates left by step k-1 (or the init kernel)
@@ -372,15 +375,15 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     // ---- 2. the winner's row, the own rows' multipliers (eq. 15), then the
     //         first group of own rows
     const gptr<const T> Wp = W + (int64_t)rp * ldw;
-    VT pw[kNch];
+    VT pw[NCH];
 #pragma unroll
-    for (int c = 0; c < kNch; ++c)
+    for (int c = 0; c < NCH; ++c)
         pw[c] = *reinterpret_cast<gptr<const VT>>(Wp + (c < nch ? c : 0) * tpr * VE + tc * VE);
     VT pwb;
     if constexpr (RHS) pwb = *reinterpret_cast<gptr<const VT>>(Wp + bcol);
     // (slots without a row read the pivot row, which nobody writes this step)
     T q_own = W[(int64_t)(nsr > 0 ? r0 + min(t, nsr - 1) : rp) * ldw + cp];
-    VT wb[B][kNch];
+    VT wb[B][NCH];
     VT wbb[B];   // RHS: the B chunk of each row slot
     const bool early = kEarlyRows<NT> && !det_only;
     if constexpr (kEarlyRows<NT>) {
@@ -392,7 +395,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
             const bool use = early && x < min(U, nsr) && r0 + x != rp;
             const gptr<const T> Wi = W + (int64_t)(use ? r0 + x : rp) * ldw;
 #pragma unroll
-            for (int c = 0; c < kNch; ++c)
+            for (int c = 0; c < NCH; ++c)
                 wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + (c < nch ? c : 0) * tpr * VE + tc * VE));
             if constexpr (RHS) wbb[g] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + bcol));
         }
@@ -422,11 +425,11 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
 
     // ---- 3. the pivot row divided by the pivot (eq. 14) and the new logical
     //         column indices, for this thread's columns
-    T prow[kNch][VE];
-    int ckey[kNch][VE];
+    T prow[NCH][VE];
+    int ckey[NCH][VE];
     bool slow = false;
 #pragma unroll
-    for (int c = 0; c < kNch; ++c) {
+    for (int c = 0; c < NCH; ++c) {
         const int j0 = c * tpr * VE + tc * VE;
         if (FULL || c < nch) {   // the same for the whole workgroup: a scalar branch
 #pragma unroll
@@ -450,7 +453,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     }
     if (slow) {   // operands outside the corrected-quotient range: IEEE division
 #pragma unroll
-        for (int c = 0; c < kNch; ++c)
+        for (int c = 0; c < NCH; ++c)
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
                 const int j = c * tpr * VE + tc * VE + e;
@@ -463,7 +466,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
     }
     if (rb == 0 && rsub == 0) {
 #pragma unroll
-        for (int c = 0; c < kNch; ++c)
+        for (int c = 0; c < NCH; ++c)
 #pragma unroll
             for (int e = 0; e < VE; ++e) {
                 const int j = c * tpr * VE + tc * VE + e;
@@ -513,7 +516,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
         if constexpr (kEarlyRows<NT>) {
             if (fix) {   // the previous pivot row: its deferred eq. 14 first
 #pragma unroll
-                for (int c = 0; c < kNch; ++c)
+                for (int c = 0; c < NCH; ++c)
 #pragma unroll
                     for (int e = 0; e < VE; ++e) {
                         const int j = c * tpr * VE + tc * VE + e;
@@ -526,7 +529,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
             // store has completed, so a register shared by all chunks would
             // serialise them
 #pragma unroll
-            for (int c = 0; c < kNch; ++c)
+            for (int c = 0; c < NCH; ++c)
                 if (FULL || c < nch)
 #pragma unroll
                     for (int e = 0; e < VE; ++e)
@@ -541,13 +544,13 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
                 }
             }
 #pragma unroll
-            for (int c = 0; c < kNch; ++c)
+            for (int c = 0; c < NCH; ++c)
                 if (FULL || c < nch) row_st<NTL>(reinterpret_cast<gptr<VT>>(Wi + c * tpr * VE + tc * VE), wb[g][c]);
             if constexpr (RHS)
                 if (bown) row_st<NTL>(reinterpret_cast<gptr<VT>>(Wi + bcol), wbb[g]);
         } else {
 #pragma unroll
-            for (int c = 0; c < kNch; ++c) {
+            for (int c = 0; c < NCH; ++c) {
                 if (c < nch) {
                     const int j0 = c * tpr * VE + tc * VE;
                     VT w = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + j0));
@@ -574,7 +577,7 @@ gj_big_step(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, co
             if (all || (use && srl[x] >= 0)) {
                 const gptr<const T> Wi = W + (int64_t)(use ? i : rp) * ldw;
 #pragma unroll
-                for (int c = 0; c < kNch; ++c)
+                for (int c = 0; c < NCH; ++c)
                     if (all || c < nch)
                         wb[g][c] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + (c < nch ? c : 0) * tpr * VE + tc * VE));
                 if constexpr (RHS) wbb[g] = row_ld<NTL>(reinterpret_cast<gptr<const VT>>(Wi + bcol));
@@ -791,7 +794,8 @@ gj_big_gather(const BigDesc *__restrict__ descs, const int2 *__restrict__ bmap, 
 
 // ---------------------------------------------------------------- launchers
 
-template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS = false, int RULE = 0>
+template <typename T, int NT, bool NTL, bool FULL, bool CNT, bool RHS = false, int RULE = 0,
+          int NCH = kNch>
 static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDesc &single,
                             const int *grid_per_step,
                             int grid_init, int grid_finish, int max_n, int gather_grid,
@@ -805,7 +809,7 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
         if (e != hipSuccess) return e;
     }
     for (int k = 0; k < max_n; ++k) {
-        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL, CNT, RHS, RULE>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
+        hipLaunchKernelGGL((gj_big_step<T, NT, NTL, FULL, CNT, RHS, RULE, NCH>), dim3(grid_per_step ? grid_per_step[k] : grid_init),
                            dim3(NT), 0, s, descs, bmap, single, k, zero_tol, eps_default, det_only,
                            run_flag);
         e = hipGetLastError();
@@ -826,16 +830,20 @@ static hipError_t run_big_t(const BigDesc *descs, const int2 *bmap, const BigDes
     return e;
 }
 
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, bool rhs, int rule,
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, int full, bool counted, bool rhs, int rule,
                       const BigDesc *descs, const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
                       void *const *events, const int32_t *run_flag, hipStream_t s) {
-    // the counter is compiled in for full chunks below 1024 threads only; the
-    // extra right-hand-side chunk for FP64 full chunks below 1024 threads,
-    // without the counter
-    if (counted && !(full && nt < 1024)) return hipErrorInvalidValue;
-    if (rhs && (fp32 || counted || !full || nt >= 1024)) return hipErrorInvalidValue;
+    // full: 0 (per-chunk tests), 8 or 4 (every row fills exactly that many
+    // chunks per thread; 4: 256 and 512 threads, rule 0, no counter, no B).
+    // The counter is compiled in for 8 full chunks below 1024 threads only;
+    // the extra right-hand-side chunk for FP64 with 8 full chunks below 1024
+    // threads, without the counter
+    if (full != 0 && full != 4 && full != kNch) return hipErrorInvalidValue;
+    if (full == 4 && (counted || rhs || rule != 0 || nt >= 1024)) return hipErrorInvalidValue;
+    if (counted && !(full == kNch && nt < 1024)) return hipErrorInvalidValue;
+    if (rhs && (fp32 || counted || full != kNch || nt >= 1024)) return hipErrorInvalidValue;
     // the other pivot rules: FP64, per-chunk tests, no counter, B right after A
     if (rule != 0 && (fp32 || counted || full || rhs || rule > 2)) return hipErrorInvalidValue;
 #define GJ_BIG_ARGS descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n, gather_grid, \
@@ -858,6 +866,9 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted,
         if (counted)                                                                              \
             return nt_loads ? run_big_t<TT, NTV, true, true, true>(GJ_BIG_ARGS)                   \
                             : run_big_t<TT, NTV, false, true, true>(GJ_BIG_ARGS);                 \
+        if (full == 4)                                                                            \
+            return nt_loads ? run_big_t<TT, NTV, true, true, false, false, 0, 4>(GJ_BIG_ARGS)     \
+                            : run_big_t<TT, NTV, false, true, false, false, 0, 4>(GJ_BIG_ARGS);   \
     }                                                                                             \
     return nt_loads ? (full ? run_big_t<TT, NTV, true, true, false>(GJ_BIG_ARGS)                  \
                             : run_big_t<TT, NTV, true, false, false>(GJ_BIG_ARGS))                \

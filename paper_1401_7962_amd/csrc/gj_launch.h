@@ -30,13 +30,14 @@ hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks
                          hipStream_t s);
 
 // Streaming path: init, one step launch per k, finish, gather.  nt_loads:
-// nontemporal row loads; full: every matrix uses all register chunks;
-// counted: some descriptor leaves work units to the per-step counter
-// (needs full and nt < 1024); rhs: a solve whose B is an extra partial
-// register chunk after A's full ones (FP64, full, nt < 1024, not counted);
-// rule: pivot rule of every descriptor (0 full; 1, 2 need FP64 and none of
-// full, counted, rhs).
-hipError_t launch_big(bool fp32, int nt, bool nt_loads, bool full, bool counted, bool rhs, int rule,
+// nontemporal row loads; full: 8 or 4 when every matrix's rows fill exactly
+// that many register chunks per thread, else 0 (4: rule 0, nt < 1024, not
+// counted, no rhs); counted: some descriptor leaves work units to the
+// per-step counter (needs 8 full chunks and nt < 1024); rhs: a solve whose
+// B is an extra partial register chunk after A's 8 full ones (FP64,
+// nt < 1024, not counted); rule: pivot rule of every descriptor (0 full;
+// 1, 2 need FP64 and none of full, counted, rhs).
+hipError_t launch_big(bool fp32, int nt, bool nt_loads, int full, bool counted, bool rhs, int rule,
                       const BigDesc *descs,
                       const int2 *bmap,
                       const BigDesc &single, const int *grid_per_step, int grid_init,

@@ -130,10 +130,11 @@ def test_streaming_work_units(gj, n, rows, stat, monkeypatch):
     assert r["det_sign"] == want[3]["det_sign"]
 
 
-@pytest.mark.parametrize("n,chunks", [(1100, 4), (1100, 2), (2100, 4), (1500, 1)])
+@pytest.mark.parametrize("n,chunks", [(1100, 4), (1100, 2), (2100, 4), (1500, 1), (2000, 4)])
 def test_streaming_chunks_per_thread(gj, n, chunks, monkeypatch):
     """Wider rows than the default shape (fewer register chunks per thread,
-    more threads per row; 1 chunk clamps the row to the workgroup): the
+    more threads per row; 1 chunk clamps the row to the workgroup; at 2000
+    with 4 chunks every thread fills all 4, the 4-chunk step kernel): the
     inverse and the pivots must still match the oracle bit for bit."""
     monkeypatch.setenv("GJ_BIG_CHUNKS", str(chunks))
     A = inputs.rng_for(0, 3300 + n + chunks).standard_normal((n, n))

@@ -93,18 +93,20 @@ def test_refined_counted_units(gj, stat, monkeypatch):
     assert _rel(X, Xo) <= 1e-12
 
 
-@pytest.mark.parametrize("n", [1100, 2100])
+@pytest.mark.parametrize("n", [1100, 2100, 2000, 4000])
 def test_refined_chunks_per_thread(gj, n, monkeypatch):
     """The FP32 elimination's row shape from the tuning table (4 register
-    chunks per thread in these buckets) against the 8-chunk shape: the same
-    FP32 pivot sequence as the oracle, and the same refined inverse bit for
-    bit (each element's update does not depend on which thread holds it)."""
+    chunks per thread in these buckets; at 2000 and 4000 the rows fill all 4,
+    which selects the 4-chunk step kernel) against the 8-chunk shape: the
+    same FP32 pivot sequence as the oracle, and the same refined inverse bit
+    for bit (each element's update does not depend on which thread holds
+    it)."""
     A = inputs.conditioned(n, 1e4, inputs.rng_for(0, 6070 + n))
     X4, ip4, jp4, r4 = _refined(gj, A)
     monkeypatch.setenv("GJ_BIG_CHUNKS", "8")
     X8, ip8, jp8, r8 = _refined(gj, A)
     assert r4["code"] == 0 and r8["code"] == 0, (r4, r8)
-    _, i32, j32, _ = oracle.gj_invert_f32(A.astype(np.float32))
+    _, i32, j32, _ = oracle.gj_invert_f32_par(A.astype(np.float32))
     assert np.array_equal(ip4, i32) and np.array_equal(jp4, j32)
     assert np.array_equal(ip8, i32) and np.array_equal(jp8, j32)
     assert np.array_equal(X4, X8)
