@@ -183,6 +183,18 @@ BigShape big_shape(int n, bool fp32, int nt, int ncol = 0, int rows = 0) {
     return s;
 }
 
+// Row shape of a single matrix.  The table's buckets up to 1024 were tuned on
+// packed batches, where many members share a launch and few workgroups per
+// member pay; one matrix of that order needs the most workgroups instead: FP64
+// us per step, table rows / one register group per workgroup: 512: 20.7 / 10.4,
+// 768: 20.3 / 10.7, 1024: 21.2 / 11.0 (FP32: 22.3 / 15.1, 19.9 / 14.3,
+// 22.6 / 15.4); above 1024 the table's single-matrix rows stay (1536: 14.3
+// against 19.7).  GJ_BIG_ROWS still overrides.
+BigShape single_shape(int n, bool fp32, int nt, int ncol = 0) {
+    const int rows = (n <= 1024 && env_int("GJ_BIG_ROWS", 0) <= 0) ? 1 : 0;
+    return big_shape(n, fp32, nt, ncol, rows);
+}
+
 // Nontemporal row loads and stores once the array swept per step clearly
 // outgrows the 256 MB Infinity Cache.  Measured on MI355X (FP64, ms per
 // inversion, cached / nontemporal): 6144^2 = 288 MiB 758 / 841, 6656^2 =
@@ -553,7 +565,7 @@ size_t single_ws(int n, const Opts &o, bool det_only) {
     if (use_blocked(n, o, det_only)) {
         need = blk_layout(n).end;
     } else if (n > kOnchipMax || o.rule != 0) {
-        BigShape s = big_shape(n, false, big_threads(n, false));
+        BigShape s = single_shape(n, false, big_threads(n, false));
         need = big_bufs(s, false, 0).end;
     }
     if (o.want_resid && !det_only) need = a256(need) + resid_ws(n);
@@ -567,7 +579,7 @@ size_t single_ws(int n, const Opts &o, bool det_only) {
 // otherwise [A | B] is shaped as one wider array, B right after A.
 BigShape big_shape_solve(int n, int m, int rule, bool &rhs) {
     const int nt = big_threads(n, false);
-    BigShape s = big_shape(n, false, nt);
+    BigShape s = single_shape(n, false, nt);
     rhs = rule == 0 && big_full(s, false) && nt < 1024 && m <= s.tpr * 2;
     if (rhs) {
         s.rhs0 = 8 * s.tpr * 2;
@@ -576,7 +588,7 @@ BigShape big_shape_solve(int n, int m, int rule, bool &rhs) {
         s.ustat = s.share;                     // the extra chunk is built without the counter
         return s;
     }
-    return big_shape(n, false, big_threads(n + m, false), n + m);
+    return single_shape(n, false, big_threads(n + m, false), n + m);
 }
 
 size_t solve_ws(int n, int m, int rule) {
@@ -634,7 +646,7 @@ gj_status run_single(int n, const double *A, int64_t lda, double *X, int64_t ldx
         return GJ_OK;
     }
     const int nt = big_threads(n, fp32);
-    BigShape sh = big_shape(n, fp32, nt);
+    BigShape sh = single_shape(n, fp32, nt);
     if (o.rule != 0) sh.ustat = sh.share;   // the other rules are built without the counter
     BigBufs bb = big_bufs(sh, fp32, 0);
     if (ws_bytes < bb.end) return GJ_E_WORKSPACE;
@@ -678,7 +690,7 @@ RefinedLayout refined_layout(int n, bool acc = false, bool blocked = false) {
     if (n > kOnchipMax && blocked) {
         c = blk_layout(n, true, c).end;             // FP32 elimination with delayed updates
     } else if (n > kOnchipMax) {
-        BigShape s = big_shape(n, true, big_threads(n, true));
+        BigShape s = single_shape(n, true, big_threads(n, true));
         c = big_bufs(s, true, c).end;
     }
     // the FP64 fallback's buffers overlay the second iterate and R: it runs
@@ -687,7 +699,7 @@ RefinedLayout refined_layout(int n, bool acc = false, bool blocked = false) {
     L.over64 = c;
     size_t over = 2 * n2;
     if (n > kOnchipMax) {
-        BigShape s = big_shape(n, false, big_threads(n, false));
+        BigShape s = single_shape(n, false, big_threads(n, false));
         over = std::max(over, big_bufs(s, false, 0).end);
     }
     L.r = a256(c + n2);
@@ -753,7 +765,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         if (o.events && o.events[1]) GJ_TRY(hipEventRecord((hipEvent_t)o.events[1], s));
     } else {
         const int nt = big_threads(n, true);
-        BigShape sh = big_shape(n, true, nt);
+        BigShape sh = single_shape(n, true, nt);
         BigBufs bb = big_bufs(sh, true, L.big32);
         d32 = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
         GJ_TRY(launch_big(true, nt, big_nt_loads(big_swept_bytes(sh, true)), big_full_chunks(sh, true), big_counted(sh), false, 0,
@@ -861,7 +873,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
                              ctl_run_fallback(ctl), s));
     } else {
         const int nt = big_threads(n, false);
-        BigShape sh = big_shape(n, false, nt);
+        BigShape sh = single_shape(n, false, nt);
         BigBufs bb = big_bufs(sh, false, L.over64);
         BigDesc d = make_desc(sh, bb, w, A, lda, det_only ? nullptr : X, ldx, ipiv, jpiv, res);
         GJ_TRY(launch_big(false, nt, big_nt_loads(big_swept_bytes(sh, false)), big_full_chunks(sh, false), big_counted(sh), false, 0,
@@ -1626,7 +1638,7 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
         if (blocked)
             off = a256(blk_layout(n).end);
         else if (n > kOnchipMax || o.rule != 0)
-            off = a256(big_bufs(big_shape(n, false, big_threads(n, false)), false, 0).end);
+            off = a256(big_bufs(single_shape(n, false, big_threads(n, false)), false, 0).end);
         return run_resid(n, A, lda, X, ldx, res, (char *)ws + off, s);
     } catch (...) {
         return GJ_E_HIP;
