@@ -134,7 +134,7 @@ int big_threads(int n, bool fp32) {
     return 1024;
 }
 
-BigShape big_shape(int n, bool fp32, int nt, int ncol = 0, int rows = 0) {
+BigShape big_shape(int n, bool fp32, int nt, int ncol = 0, int rows = 0, int chunks_want = 0) {
     BigShape s;
     const int ve = fp32 ? 4 : 2;
     if (ncol < n) ncol = n;
@@ -146,7 +146,7 @@ BigShape big_shape(int n, bool fp32, int nt, int ncol = 0, int rows = 0) {
     // thread (8 by default, so that every thread's registers are used; a
     // wavefront may span several rows)
     const TuneEntry *te = tuned(fp32, n);
-    int chunks = env_int("GJ_BIG_CHUNKS", 0);
+    int chunks = chunks_want > 0 ? chunks_want : env_int("GJ_BIG_CHUNKS", 0);
     if (chunks < 1 || chunks > 8) chunks = te ? te->chunks : 8;
     int need = (ncol + chunks * ve - 1) / (chunks * ve);
     int tpr = 4;
@@ -183,17 +183,6 @@ BigShape big_shape(int n, bool fp32, int nt, int ncol = 0, int rows = 0) {
     return s;
 }
 
-// Row shape of a single matrix.  The table's buckets up to 1024 were tuned on
-// packed batches, where many members share a launch and few workgroups per
-// member pay; one matrix of that order needs the most workgroups instead: FP64
-// us per step, table rows / one register group per workgroup: 512: 20.7 / 10.4,
-// 768: 20.3 / 10.7, 1024: 21.2 / 11.0 (FP32: 22.3 / 15.1, 19.9 / 14.3,
-// 22.6 / 15.4); above 1024 the table's single-matrix rows stay (1536: 14.3
-// against 19.7).  GJ_BIG_ROWS still overrides.
-BigShape single_shape(int n, bool fp32, int nt, int ncol = 0) {
-    const int rows = (n <= 1024 && env_int("GJ_BIG_ROWS", 0) <= 0) ? 1 : 0;
-    return big_shape(n, fp32, nt, ncol, rows);
-}
 
 // Nontemporal row loads and stores once the array swept per step clearly
 // outgrows the 256 MB Infinity Cache.  Measured on MI355X (FP64, ms per
@@ -228,6 +217,29 @@ int big_full_chunks(const BigShape &s, bool fp32) {
     if (ch == 8) return 8;
     if (ch == 4 && s.nt < 1024 && !big_counted(s)) return 4;
     return 0;
+}
+
+// Row shape of a single matrix.  The table's buckets up to 1024 were tuned on
+// packed batches, where many members share a launch and few workgroups per
+// member pay; one matrix of that order needs the most workgroups instead: FP64
+// us per step, table rows / one register group per workgroup: 512: 20.7 / 10.4,
+// 768: 20.3 / 10.7, 1024: 21.2 / 11.0 (FP32: 22.3 / 15.1, 19.9 / 14.3,
+// 22.6 / 15.4); above 1024 the table's single-matrix rows stay (1536: 14.3
+// against 19.7).  Up to 2048, rows that fill exactly 4 register chunks (twice
+// the threads per row) take the 4-chunk kernel: FP64 us per step, 8 / 4
+// chunks: 256: 10.2 / 7.5, 512: 10.3 / 7.6, 1024: 11.0 / 9.3, 2048: 15.8 /
+// 14.2 (FP32 at 256-1024: 15.1-15.3 / 9.7-10.1); where 4 chunks would not be
+// filled (1536: 14.3 / 14.7) the 8-chunk shape stays.  allow4 = false keeps
+// the 8-chunk shape (the solve's extra right-hand-side chunk needs it).
+// GJ_BIG_ROWS and GJ_BIG_CHUNKS still override.
+BigShape single_shape(int n, bool fp32, int nt, int ncol = 0, bool allow4 = true) {
+    const int rows = (n <= 1024 && env_int("GJ_BIG_ROWS", 0) <= 0) ? 1 : 0;
+    BigShape s = big_shape(n, fp32, nt, ncol, rows);
+    if (allow4 && n <= 2048 && env_int("GJ_BIG_CHUNKS", 0) <= 0 && big_full_chunks(s, fp32) != 4) {
+        const BigShape s4 = big_shape(n, fp32, nt, ncol, rows, 4);
+        if (big_full_chunks(s4, fp32) == 4) s = s4;
+    }
+    return s;
 }
 
 // Byte layout of one matrix's streaming-path buffers, relative to `base`.
@@ -579,7 +591,7 @@ size_t single_ws(int n, const Opts &o, bool det_only) {
 // otherwise [A | B] is shaped as one wider array, B right after A.
 BigShape big_shape_solve(int n, int m, int rule, bool &rhs) {
     const int nt = big_threads(n, false);
-    BigShape s = single_shape(n, false, nt);
+    BigShape s = single_shape(n, false, nt, 0, false);
     rhs = rule == 0 && big_full(s, false) && nt < 1024 && m <= s.tpr * 2;
     if (rhs) {
         s.rhs0 = 8 * s.tpr * 2;
@@ -588,7 +600,7 @@ BigShape big_shape_solve(int n, int m, int rule, bool &rhs) {
         s.ustat = s.share;                     // the extra chunk is built without the counter
         return s;
     }
-    return single_shape(n, false, big_threads(n + m, false), n + m);
+    return single_shape(n, false, big_threads(n + m, false), n + m, false);
 }
 
 size_t solve_ws(int n, int m, int rule) {
