@@ -674,6 +674,59 @@ def bench_solve(n: int = 4096, m: int = 16, reps: int = 3):
             "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def bench_single_orders(sizes=(256, 512, 1024, 2048), reps: int = 3):
+    """One matrix of moderate order (the headline's input family): plain FP64
+    and FP32 + FP64 refinement, ms per inversion and the elimination's us per
+    step (HIP events around the step launches), with the FP64 result checked
+    bit for bit against the oracle (its OpenMP form, bitwise the serial
+    oracle) and the oracle's time on all host cores."""
+    import torch
+    import oracle
+    import paper_1401_7962_amd as gj
+    from paper_1401_7962_amd import inputs
+    out = {}
+    stream = torch.cuda.current_stream()
+    for n in sizes:
+        A_h = inputs.single_dominant(n)
+        A = torch.from_numpy(A_h).to("cuda")
+        row = {}
+        for name, prec in (("plain_fp64", gj.GJ_PREC_FP64), ("fp32_refined", gj.GJ_PREC_FP32_REFINED)):
+            o = gj.make_opts(precision=prec)
+            X = torch.empty_like(A)
+            ip = torch.empty(n, dtype=torch.int32, device="cuda")
+            jp = torch.empty_like(ip)
+            res = torch.empty(gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+            ws = torch.empty(gj.gj_workspace_size(gj.GJ_OP_INVERT, n, None, o), dtype=torch.uint8,
+                             device="cuda")
+            gj.gj_invert(A, X, ip, jp, res, o, ws)
+            torch.cuda.synchronize()
+            e = _events(4 * reps, stream)
+            for k in range(reps):
+                so = gj.make_opts(precision=prec,
+                                  step_events=(ctypes_ptr(e[4 * k + 1]), ctypes_ptr(e[4 * k + 2])))
+                e[4 * k].record()
+                gj.gj_invert(A, X, ip, jp, res, so, ws)
+                e[4 * k + 3].record()
+            torch.cuda.synchronize()
+            ms = min(e[4 * k].elapsed_time(e[4 * k + 3]) for k in range(reps))
+            steps_ms = min(e[4 * k + 1].elapsed_time(e[4 * k + 2]) for k in range(reps))
+            r = gj.results_to_dicts(res)[0]
+            row[name] = {"ms": round(ms, 3), "us_per_step": round(steps_ms * 1e3 / n, 2),
+                         "code": r["code"], "refine_iters": r["refine_iters"]}
+            if prec == gj.GJ_PREC_FP64:
+                t0 = time.perf_counter()
+                Xo, io, jo, ro = oracle.gj_invert_f64_par(A_h)
+                row["oracle_all_cores_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+                row[name]["bitwise_equal_to_oracle"] = bool(
+                    X.cpu().numpy().tobytes() == Xo.tobytes()
+                    and np.array_equal(ip.cpu().numpy(), io) and np.array_equal(jp.cpu().numpy(), jo)
+                    and r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"])
+            del ws
+        out[str(n)] = row
+    out["oracle_threads"] = oracle.host_threads()
+    return out
+
+
 def bench_blocked(sizes=(4096, 8192), reps: int = 3):
     """Delayed updates (GJ_FLAG_BLOCKED) against the unblocked elimination on
     the same input (the headline's at 4096, a diagonally weighted uniform one
@@ -842,6 +895,7 @@ LEGS = {"latency_small": lambda: bench_latency_small(),
         "pivot_rules": lambda: bench_pivot_rules(),
         "accuracy_exact_4096": lambda: bench_accuracy_exact(),
         "blocked": lambda: bench_blocked(),
+        "single_orders": lambda: bench_single_orders(),
         "gemm_f64_8192": lambda: bench_gemm_f64()}
 
 
@@ -940,6 +994,9 @@ def main():
         torch.cuda.empty_cache()
         extras["blocked"] = bench_blocked()
         print("bench: blocked elimination done", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extras["single_orders"] = bench_single_orders()
+        print("bench: single matrices of moderate order done", file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         out["extras"] = extras
         out["host"] = host_info()
