@@ -207,15 +207,15 @@ bool big_full(const BigShape &s, bool fp32) {
     const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
     return (s.ncol + per - 1) / per == 8;
 }
-// The step kernel's chunk count for one matrix: 8 when its rows fill all 8
-// chunks; 4 when they fill exactly 4 (below 1024 threads; such a shape has no
-// counted units), so that no unused chunk is loaded or looped over; else 0
-// (the 8-chunk kernel with per-chunk tests).
+// The step kernel's chunk count for one matrix: the number of chunks its rows
+// fill, 8 or (below 1024 threads; such shapes have no counted units) 3-7, so
+// that no unused chunk is loaded or looped over; else 0 (the 8-chunk kernel
+// with per-chunk tests).
 int big_full_chunks(const BigShape &s, bool fp32) {
     const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
     const int64_t ch = (s.ncol + per - 1) / per;
     if (ch == 8) return 8;
-    if (ch == 4 && s.nt < 1024 && !big_counted(s)) return 4;
+    if (ch >= 3 && ch < 8 && s.nt < 1024 && !big_counted(s)) return (int)ch;
     return 0;
 }
 

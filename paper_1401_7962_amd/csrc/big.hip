@@ -91,8 +91,8 @@ template <typename VT, typename T>
 __device__ inline void vset(VT &x, int e, T v) { reinterpret_cast<T *>(&x)[e] = v; }
 
 // Column chunks per thread of the step kernel (its NCH): n <= NCH * V * threads-per-row.
-// 8 in general; a shape whose rows fill exactly 4 chunks per thread gets a 4-chunk
-// kernel, whose loops and register arrays then hold no unused chunk.
+// 8 in general; a shape whose rows fill exactly 3-7 chunks per thread gets a kernel
+// of that many, whose loops and register arrays then hold no unused chunk.
 constexpr int kNch = 8;
 // Rows a thread holds in registers at once in the step kernel (their loads
 // are in flight together; the first group is requested before the candidate
@@ -835,19 +835,24 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, int full, bool counted, 
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
                       void *const *events, const int32_t *run_flag, hipStream_t s) {
-    // full: 0 (per-chunk tests), 8 or 4 (every row fills exactly that many
-    // chunks per thread; 4: 256 and 512 threads, rule 0, no counter, no B).
-    // The counter is compiled in for 8 full chunks below 1024 threads only;
-    // the extra right-hand-side chunk for FP64 with 8 full chunks below 1024
+    // full: 0 (per-chunk tests) or the chunk count 3-8 that every row fills
+    // exactly (below 8: 256 and 512 threads, rule 0, no counter, no B).  The
+    // counter is compiled in for 8 full chunks below 1024 threads only; the
+    // extra right-hand-side chunk for FP64 with 8 full chunks below 1024
     // threads, without the counter
-    if (full != 0 && full != 4 && full != kNch) return hipErrorInvalidValue;
-    if (full == 4 && (counted || rhs || rule != 0 || nt >= 1024)) return hipErrorInvalidValue;
+    if (full != 0 && (full < 3 || full > kNch)) return hipErrorInvalidValue;
+    if (full != 0 && full != kNch && (counted || rhs || rule != 0 || nt >= 1024))
+        return hipErrorInvalidValue;
     if (counted && !(full == kNch && nt < 1024)) return hipErrorInvalidValue;
     if (rhs && (fp32 || counted || full != kNch || nt >= 1024)) return hipErrorInvalidValue;
     // the other pivot rules: FP64, per-chunk tests, no counter, B right after A
     if (rule != 0 && (fp32 || counted || full || rhs || rule > 2)) return hipErrorInvalidValue;
 #define GJ_BIG_ARGS descs, bmap, single, grid_per_step, grid_init, grid_finish, max_n, gather_grid, \
                     zero_tol, eps_default, det_only, events, run_flag, s
+#define GJ_BIG_NCH(TT, NTV, C)                                                                    \
+    case C:                                                                                       \
+        return nt_loads ? run_big_t<TT, NTV, true, true, false, false, 0, C>(GJ_BIG_ARGS)         \
+                        : run_big_t<TT, NTV, false, true, false, false, 0, C>(GJ_BIG_ARGS)
 #define GJ_BIG_CASE(TT, NTV)                                                                      \
     if constexpr (!std::is_same<TT, float>::value) {                                              \
         if (rule == 1)                                                                            \
@@ -866,9 +871,11 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, int full, bool counted, 
         if (counted)                                                                              \
             return nt_loads ? run_big_t<TT, NTV, true, true, true>(GJ_BIG_ARGS)                   \
                             : run_big_t<TT, NTV, false, true, true>(GJ_BIG_ARGS);                 \
-        if (full == 4)                                                                            \
-            return nt_loads ? run_big_t<TT, NTV, true, true, false, false, 0, 4>(GJ_BIG_ARGS)     \
-                            : run_big_t<TT, NTV, false, true, false, false, 0, 4>(GJ_BIG_ARGS);   \
+        switch (full) {                                                                           \
+            GJ_BIG_NCH(TT, NTV, 3); GJ_BIG_NCH(TT, NTV, 4); GJ_BIG_NCH(TT, NTV, 5);              \
+            GJ_BIG_NCH(TT, NTV, 6); GJ_BIG_NCH(TT, NTV, 7);                                       \
+            default: break;                                                                       \
+        }                                                                                         \
     }                                                                                             \
     return nt_loads ? (full ? run_big_t<TT, NTV, true, true, false>(GJ_BIG_ARGS)                  \
                             : run_big_t<TT, NTV, true, false, false>(GJ_BIG_ARGS))                \
@@ -888,6 +895,7 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, int full, bool counted, 
         }
     }
 #undef GJ_BIG_CASE
+#undef GJ_BIG_NCH
 #undef GJ_BIG_ARGS
     return hipErrorInvalidValue;
 }
