@@ -85,10 +85,21 @@ def test_onchip_sizes(gj, n):
     _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n}")
 
 
-@pytest.mark.parametrize("n", [129, 200, 257, 333, 512, 777, 1000])
+@pytest.mark.parametrize("n", [129, 200, 257, 333, 440, 512, 777, 1000, 1400])
 def test_streaming_sizes(gj, n):
+    """Orders whose rows fill 4 (200, 512, 777, 1000), 5 (129, 257), 6 (333,
+    1400) and 7 (440) register chunks per thread: each runs the step kernel
+    of its own chunk count."""
     A = inputs.rng_for(0, 3000 + n).standard_normal((n, n))
     _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64(A), f"n={n}")
+
+
+@pytest.mark.parametrize("n", [2600, 3500])
+def test_streaming_sizes_large(gj, n):
+    """256 threads per row filling 6 (2600) and 7 (3500) chunks, against the
+    oracle's OpenMP form (bitwise the serial oracle)."""
+    A = inputs.rng_for(0, 3000 + n).standard_normal((n, n))
+    _assert_same(A, _run_invert(gj, A), oracle.gj_invert_f64_par(A), f"n={n}")
 
 
 @pytest.mark.parametrize("n,nt,rows", [(300, 1, 0), (777, 1, 0), (1000, 1, 3), (1000, 0, 64),
