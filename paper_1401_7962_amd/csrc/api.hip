@@ -776,6 +776,62 @@ RefinedLayout refined_layout(int n, bool acc = false, bool blocked = false) {
 
 #define GJ_TRY(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) return hip_fail(e_); } while (0)
 
+// A second stream per device.  The refined path's FP64 fallback and its
+// determinant stage exclude each other (both flags are set before either
+// runs, and each touches the buffers they share only when its flag is set),
+// so outside graph capture the fallback goes to this stream and overlaps the
+// determinant stage: when it is not needed, its n step launches return at
+// once (about 1.8 us each), time the determinant stage hides.  Under capture,
+// and for gj_invert_noalloc (which creates nothing), the launches stay in
+// order on the caller's stream.
+std::mutex g_side_mu;
+hipStream_t g_side[64] = {nullptr};
+thread_local bool g_no_side = false;
+
+hipStream_t side_stream_for(hipStream_t s) {
+    if (g_no_side) return nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (s) {
+        hipDevice_t sd = 0;
+        if (hipStreamGetDevice(s, &sd) != hipSuccess || (int)sd != dev) return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_side_mu);
+    if (!g_side[dev] && hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking) != hipSuccess) {
+        g_side[dev] = nullptr;
+        return nullptr;
+    }
+    return g_side[dev];
+}
+
+// The fork of the caller's stream s onto the side stream and the join back.
+struct SideFork {
+    hipStream_t s, fs;                      // fs: the stream the forked work goes to
+    hipEvent_t fork = nullptr, join = nullptr;
+    explicit SideFork(hipStream_t s_) : s(s_), fs(s_) {
+        hipStream_t side = side_stream_for(s);
+        if (!side) return;
+        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+            return;
+        if (hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(side, fork, 0) == hipSuccess)
+            fs = side;
+    }
+    hipError_t join_back() {
+        if (fs == s) return hipSuccess;
+        hipError_t e = hipEventRecord(join, fs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+        fs = s;
+        return e;
+    }
+    ~SideFork() {   // destruction of a pending event is deferred until it completes
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+    }
+};
+
 // Eliminate in FP32 (the pivots and X0), refine X in FP64, FP64 determinant.
 gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int64_t ldx,
                              int32_t *ipiv, int32_t *jpiv, gj_result *res, const Opts &o, char *w,
@@ -918,12 +974,14 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
         GJ_TRY(launch_refine_finish(ctl, 1, __builtin_inf(), 1, s));
     }
 
-    // 3. fallback: the plain FP64 elimination, only when flagged
+    // 3. fallback: the plain FP64 elimination, only when flagged (on the side
+    // stream where there is one, beside the determinant stage)
+    SideFork fork(s);
     if (n <= kOnchipMax) {
         MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0, nullptr};
         GJ_TRY(launch_onchip(false, nullptr, nullptr, 0, nullptr, md, 1, A, det_only ? nullptr : X,
                              ipiv, jpiv, res, o.zero_tol, kEps64, det_only ? 1 : 0,
-                             ctl_run_fallback(ctl), s));
+                             ctl_run_fallback(ctl), fork.fs));
     } else {
         const int nt = big_threads(n, false);
         BigShape sh = single_shape(n, false, nt);
@@ -933,9 +991,9 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
                           nullptr, nullptr, d,
                           nullptr, sh.nblk, sh.nblk, n,
                           det_only ? 0 : sh.nblk, o.zero_tol, kEps64, det_only ? 1 : 0, nullptr,
-                          ctl_run_fallback(ctl), s));
+                          ctl_run_fallback(ctl), fork.fs));
     }
-    GJ_TRY(launch_fallback_mark(ctl, 1, s));
+    GJ_TRY(launch_fallback_mark(ctl, 1, fork.fs));
 
     // 4. FP64 determinant: permute A with the FP32 order, block elimination
     const int32_t *fdet = ctl_run_det(ctl);
@@ -993,6 +1051,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
     }
     GJ_TRY(launch_det_combine(nullptr, m, ctl, 1, s));
     GJ_TRY(launch_refine_iters(ctl, 1, s));
+    GJ_TRY(fork.join_back());
 
     // 5. optional residual of the returned inverse
     if (o.want_resid && !det_only) {
@@ -1716,6 +1775,10 @@ gj_status gj_invert_noalloc(int32_t n, const double *A, int64_t lda, double *X, 
         void *ws = nullptr;
         e = scratch_address(dev, &ws);
         if (e != hipSuccess) return hip_fail(e);
+        struct NoSide {   // no side stream or event is created for this call
+            NoSide() { g_no_side = true; }
+            ~NoSide() { g_no_side = false; }
+        } no_side;
         return gj_invert(n, A, lda, X, ldx, ipiv, jpiv, res, opts, ws,
                          (size_t)GJ_NOALLOC_SCRATCH_BYTES, stream);
     } catch (...) {
