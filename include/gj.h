@@ -24,7 +24,11 @@
  *   written; X must not overlap A or the workspace.
  * Stream.  `stream` is a hipStream_t (NULL = the null stream).  Every call
  *   enqueues its kernels on it and returns; results are valid once the stream
- *   has been synchronised.  The return value covers only argument checks and
+ *   has been synchronised.  Outside graph capture, the refined single-matrix
+ *   path (gj_invert, gj_det with GJ_PREC_FP32_REFINED) enqueues its FP64
+ *   fallback on a second stream of the device that the library creates once,
+ *   and makes `stream` wait for it before the call's last work: synchronising
+ *   `stream` still covers everything.  The return value covers only argument checks and
  *   launch errors; numeric outcomes (singular, non-finite) are reported per
  *   matrix in the device-side gj_result.
  * Pivots.  0-based, LAPACK xGETC2 convention: at step k rows k <-> ipiv[k] and
@@ -38,9 +42,9 @@
  *   error: the call returns GJ_OK and the matrix's gj_result says SINGULAR.
  * Threads.  Library state is read-only after load, apart from a mutex-guarded
  *   record of the batched plans uploaded into each workspace (for
- *   GJ_FLAG_REUSE_PLAN) and the per-device address of gj_invert_noalloc's
- *   array; calls on different streams with different workspaces may run
- *   concurrently.
+ *   GJ_FLAG_REUSE_PLAN), the per-device address of gj_invert_noalloc's array
+ *   and the per-device second stream; calls on different streams with
+ *   different workspaces may run concurrently.
  */
 #ifndef GJ_H
 #define GJ_H
