@@ -178,6 +178,33 @@ def test_fallback_when_fp32_underflows(gj, n):
     assert r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"]
 
 
+@pytest.mark.parametrize("n", [40, 260])
+def test_fallback_on_caller_stream(gj, n):
+    """Outside graph capture the FP64 fallback runs on the library's second
+    stream; synchronising only the caller's stream must cover it (the call
+    makes that stream wait for the second one before its last work)."""
+    import torch
+    A = inputs.rng_for(0, 6250 + n).standard_normal((n, n)) * 1e-50
+    opts = gj.make_opts(precision=gj.GJ_PREC_FP32_REFINED)
+    Ad = torch.from_numpy(A).to("cuda")
+    X = torch.full((n, n), 7.0, dtype=torch.float64, device="cuda")
+    ip = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+    jp = ip.clone()
+    res = torch.zeros(gj.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(gj.gj_workspace_size(gj.GJ_OP_INVERT, n, None, opts), dtype=torch.uint8,
+                     device="cuda")
+    torch.cuda.synchronize()
+    s2 = torch.cuda.Stream()
+    gj.gj_invert(Ad, X, ip, jp, res, opts, ws, s2)
+    s2.synchronize()
+    r = gj.results_to_dicts(res)[0]
+    Xo, io, jo, ro = oracle.gj_invert_f64(A)
+    assert r["code"] == 3
+    assert X.cpu().numpy().tobytes() == Xo.tobytes()
+    assert np.array_equal(ip.cpu().numpy(), io) and np.array_equal(jp.cpu().numpy(), jo)
+    assert r["det_mant"] == ro["det_mant"] and r["det_exp"] == ro["det_exp"]
+
+
 @pytest.mark.parametrize("n", [64, 256])
 def test_singular_through_refined_path(gj, n):
     H = inputs.sylvester_hadamard(n)
