@@ -1003,8 +1003,11 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
     for (int kb = 0, bi = 0; kb < n; kb += kDetBlock, ++bi) {
         const int nbk = std::min(kDetBlock, n - kb);
         MatDesc md{(int64_t)kb * n + kb, 0, 0, nbk, n, kDetBlock, 0, nullptr};
+        // the block in the FP32 pivot order: static pivots (an exact zero only
+        // counts as singular, as in an LU in that order)
         GJ_TRY(launch_onchip(false, nullptr, nullptr, 0, nullptr, md, 1, B, Dinv, bpiv,
-                             bpiv + kDetBlock, blockres + bi, -1.0, kEps64, 0, fdet, s));
+                             bpiv + kDetBlock, blockres + bi, 0.0, kEps64, kOnchipStaticPivots,
+                             fdet, s));
         const int mm = n - kb - nbk;
         if (mm > 0) {
             GemmArgs g1;
@@ -1421,12 +1424,13 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     uint32_t *queues = reinterpret_cast<uint32_t *>(w + E.off_queue);
     auto run_onchip_set = [&](bool fp32, const MatDesc *mats, const OnchipTask *tasks,
                               const int *cstart, const int *ccount, const double *Ab, double *Xb,
-                              int32_t *ip, int32_t *jp, gj_result *rs, double tol, double eps) -> gj_status {
+                              int32_t *ip, int32_t *jp, gj_result *rs, double tol, double eps,
+                              int mode) -> gj_status {
         GJ_TRY(launch_zero_u32(queues, kOnchipClasses, s));
         for (int c = 0; c < kOnchipClasses; ++c) {
             if (!ccount[c]) continue;
             GJ_TRY(launch_onchip_class(fp32, c, mats, tasks + cstart[c], ccount[c], queues + c, MatDesc(),
-                                       Ab, Xb, ip, jp, rs, tol, eps, 0, nullptr, s));
+                                       Ab, Xb, ip, jp, rs, tol, eps, mode, nullptr, s));
         }
         return GJ_OK;
     };
@@ -1442,7 +1446,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     if (!E.tasks.empty()) {
         st = run_onchip_set(true, reinterpret_cast<const MatDesc *>(w + E.off_mats),
                             reinterpret_cast<const OnchipTask *>(w + E.off_tasks), E.cls_start,
-                            E.cls_count, A, X, ipiv, jpiv, res, 0.0, 0.0);
+                            E.cls_count, A, X, ipiv, jpiv, res, 0.0, 0.0, 0);
         if (st != GJ_OK) return st;
     }
     if (!E.big_members.empty())
@@ -1465,7 +1469,7 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
     if (!E.tasks.empty()) {
         st = run_onchip_set(false, reinterpret_cast<const MatDesc *>(w + P.fb.off_mats),
                             reinterpret_cast<const OnchipTask *>(w + P.fb.off_tasks), E.cls_start,
-                            E.cls_count, A, X, ipiv, jpiv, res, o.zero_tol, kEps64);
+                            E.cls_count, A, X, ipiv, jpiv, res, o.zero_tol, kEps64, 0);
         if (st != GJ_OK) return st;
     }
     if (!E.big_members.empty()) {
@@ -1486,7 +1490,8 @@ gj_status run_refined_batched(int batch, const int32_t *n_host, const int64_t *o
         st = run_onchip_set(false, reinterpret_cast<const MatDesc *>(w + S.off_mats),
                             reinterpret_cast<const OnchipTask *>(w + S.off_tasks), S.cls_start,
                             S.cls_count, wd, wd, reinterpret_cast<int32_t *>(w),
-                            reinterpret_cast<int32_t *>(w) + kDetBlock, blockres, -1.0, kEps64);
+                            reinterpret_cast<int32_t *>(w) + kDetBlock, blockres, 0.0, kEps64,
+                            kOnchipStaticPivots);
         if (st != GJ_OK) return st;
         if ((st = grouped(P.det_t[sb])) != GJ_OK) return st;
         if ((st = grouped(P.det_r[sb])) != GJ_OK) return st;

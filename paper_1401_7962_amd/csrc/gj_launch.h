@@ -17,6 +17,9 @@ int env_int(const char *name, int dflt);
 constexpr int kOnchipClasses = 16;
 int onchip_class_of(int n, bool single);
 int onchip_class_kind(int c);
+// det_only bit 1 (kOnchipStaticPivots, FP64 only): step k pivots on element
+// (k, k), no search (rows and columns already in pivot order).
+constexpr int kOnchipStaticPivots = 2;
 hipError_t launch_onchip_class(bool fp32, int cls, const MatDesc *mats, const OnchipTask *tasks,
                                int ntasks, uint32_t *queue, const MatDesc &single, const double *A,
                                double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,

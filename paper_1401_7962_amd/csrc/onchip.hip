@@ -205,7 +205,10 @@ __device__ __forceinline__ void scan_argmax(const T (&v)[EA][EB], int k, int tr,
     c.key = (code >= 0) ? (((uint32_t)i << 16) | (uint32_t)j) : 0xFFFFFFFFu;
 }
 
-template <typename T, int TR, int TC, int EA, int EB, int NW>
+// STATIC: the pivot of step k is element (k, k) (the rows and columns are
+// already in pivot order, as for the refined path's determinant blocks); no
+// search, and the singular test looks at that element.
+template <typename T, int TR, int TC, int EA, int EB, int NW, bool STATIC = false>
 __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *__restrict__ A,
                                         double *__restrict__ X, int32_t *__restrict__ ipiv_all,
                                         int32_t *__restrict__ jpiv_all,
@@ -263,10 +266,12 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
     int code = GJ_RES_OK, rank = n;
 
     for (int k = 0; k < n; ++k) {
-        const T m = c.v;   // |pivot|
-        if (nf || !M::finite_(m)) { code = GJ_RES_NONFINITE; rank = k; break; }
-        if (m == (T)0 || m < tau) { code = GJ_RES_SINGULAR; rank = k; break; }
-        const int r = (int)(c.key >> 16), cc = (int)(c.key & 0xFFFFu);
+        if constexpr (!STATIC) {
+            const T m = c.v;   // |pivot|
+            if (nf || !M::finite_(m)) { code = GJ_RES_NONFINITE; rank = k; break; }
+            if (m == (T)0 || m < tau) { code = GJ_RES_SINGULAR; rank = k; break; }
+        }
+        const int r = STATIC ? k : (int)(c.key >> 16), cc = STATIC ? k : (int)(c.key & 0xFFFFu);
         const int ar = r / TR, trr = r % TR, ak = k / TR, trk = k % TR;
         const int bc = cc / TC, tcc = cc % TC, bk = k / TC, tck = k % TC;
 
@@ -342,6 +347,11 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 
         // eq. 13, in step order (every lane keeps the same product)
         const T p = L.prow[N];
+        if constexpr (STATIC) {   // the same staged value in every thread
+            const T ap = M::abs_(p);
+            if (nf || !M::finite_(ap)) { code = GJ_RES_NONFINITE; rank = k; break; }
+            if (ap == (T)0 || ap < tau) { code = GJ_RES_SINGULAR; rank = k; break; }
+        }
         det.mul(p);
         if (r != k) det.sign = -det.sign;
         if (cc != k) det.sign = -det.sign;
@@ -401,10 +411,16 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
                     for (int b = 0; b < EB; ++b) v[a][b] = pr[b];
                 }
         }
-        // fused pivot search for step k+1 over rows and columns > k
+        // fused pivot search for step k+1 over rows and columns > k (with
+        // static pivots only the barrier that keeps the next step's staging
+        // from overwriting lines another wavefront still reads)
         if (k + 1 < n) {
-            scan_argmax<T, TR, TC, EA, EB>(v, k, tr, tc, c);
-            group_argmax(c, L, t);
+            if constexpr (STATIC) {
+                group_sync<NW>();
+            } else {
+                scan_argmax<T, TR, TC, EA, EB>(v, k, tr, tc, c);
+                group_argmax(c, L, t);
+            }
         }
     }
 
@@ -469,7 +485,7 @@ __device__ __forceinline__ void gj_core(int t, const MatDesc md, const double *_
 // the host.  With mats == nullptr the kernel inverts the single matrix passed
 // by value (workgroup 0, KIND 0).
 // At least two wavefronts per SIMD: the register budget stays within 256.
-template <typename T, int KIND, int E>
+template <typename T, int KIND, int E, bool STATIC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 gj_onchip_kernel(const MatDesc *__restrict__ mats, const OnchipTask *__restrict__ tasks,
                  int ntasks, uint32_t *__restrict__ queue, const MatDesc single,
@@ -486,7 +502,7 @@ gj_onchip_kernel(const MatDesc *__restrict__ mats, const OnchipTask *__restrict_
     if (mats == nullptr) {
         if constexpr (KIND == 0) {
             if (blockIdx.x == 0)
-                gj_core<T, 16, 16, E, E, 4>(t, single, A, X, ipiv, jpiv, res, zero_tol,
+                gj_core<T, 16, 16, E, E, 4, STATIC>(t, single, A, X, ipiv, jpiv, res, zero_tol,
                                             eps_default, det_only, *reinterpret_cast<L0 *>(smem));
         }
         return;
@@ -500,14 +516,14 @@ gj_onchip_kernel(const MatDesc *__restrict__ mats, const OnchipTask *__restrict_
         const OnchipTask task = tasks[id];
         if constexpr (KIND == 0) {
             const MatDesc md = mats[task.m[0]];
-            gj_core<T, 16, 16, E, E, 4>(t, md, A, X, ipiv, jpiv, res, zero_tol, eps_default,
+            gj_core<T, 16, 16, E, E, 4, STATIC>(t, md, A, X, ipiv, jpiv, res, zero_tol, eps_default,
                                         det_only, *reinterpret_cast<L0 *>(smem));
         } else {
             const int w = t / kWave, lane = t % kWave;
             const int mi = task.m[w];
             if (mi >= 0) {
                 const MatDesc md = mats[mi];
-                gj_core<T, 8, 8, E, E, 1>(lane, md, A, X, ipiv, jpiv, res, zero_tol, eps_default,
+                gj_core<T, 8, 8, E, E, 1, STATIC>(lane, md, A, X, ipiv, jpiv, res, zero_tol, eps_default,
                                           det_only, reinterpret_cast<L1 *>(smem)[w]);
             }
         }
@@ -540,7 +556,7 @@ int onchip_class_of(int n, bool single) {
 }
 int onchip_class_kind(int c) { return c < 8 ? 0 : 1; }
 
-template <typename T, int KIND, int E>
+template <typename T, int KIND, int E, bool STATIC>
 static hipError_t launch_cls(const MatDesc *mats, const OnchipTask *tasks, int ntasks,
                              uint32_t *queue, const MatDesc &single, int grid, const double *A,
                              double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,
@@ -551,18 +567,18 @@ static hipError_t launch_cls(const MatDesc *mats, const OnchipTask *tasks, int n
         hipError_t e = hipGetDevice(&dev);
         if (e != hipSuccess) return e;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gj_onchip_kernel<T, KIND, E>, 256, 0) != hipSuccess) per = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, gj_onchip_kernel<T, KIND, E, STATIC>, 256, 0) != hipSuccess) per = 1;
         const int force = env_int("GJ_ONCHIP_PER_CU", 0);   // experiments only
         if (force > 0) per = force;
         grid = std::max(1, std::min(ntasks, cus * std::max(per, 1)));
     }
-    hipLaunchKernelGGL((gj_onchip_kernel<T, KIND, E>), dim3(grid), dim3(256), 0, s, mats, tasks,
+    hipLaunchKernelGGL((gj_onchip_kernel<T, KIND, E, STATIC>), dim3(grid), dim3(256), 0, s, mats, tasks,
                        ntasks, queue, single, A, X, ipiv, jpiv, res, zero_tol, eps_default, det_only,
                        run_flag);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool STATIC>
 static hipError_t launch_cls_t(int cls, const MatDesc *mats, const OnchipTask *tasks, int ntasks,
                                uint32_t *queue, const MatDesc &single, const double *A, double *X,
                                int32_t *ipiv, int32_t *jpiv, gj_result *res, double zero_tol,
@@ -570,8 +586,9 @@ static hipError_t launch_cls_t(int cls, const MatDesc *mats, const OnchipTask *t
                                hipStream_t s) {
 #define GJ_CLS(C, K, EE)                                                                        \
     case C:                                                                                     \
-        return launch_cls<T, K, EE>(mats, tasks, ntasks, queue, single, 1, A, X, ipiv, jpiv,    \
-                                    res, zero_tol, eps_default, det_only, run_flag, s)
+        return launch_cls<T, K, EE, STATIC>(mats, tasks, ntasks, queue, single, 1, A, X, ipiv,  \
+                                            jpiv, res, zero_tol, eps_default, det_only,         \
+                                            run_flag, s)
     switch (cls) {
         GJ_CLS(0, 0, 8); GJ_CLS(1, 0, 7); GJ_CLS(2, 0, 6); GJ_CLS(3, 0, 5);
         GJ_CLS(4, 0, 4); GJ_CLS(5, 0, 3); GJ_CLS(6, 0, 2); GJ_CLS(7, 0, 1);
@@ -587,10 +604,16 @@ hipError_t launch_onchip_class(bool fp32, int cls, const MatDesc *mats, const On
                                double *X, int32_t *ipiv, int32_t *jpiv, gj_result *res,
                                double zero_tol, double eps_default, int det_only,
                                const int32_t *run_flag, hipStream_t s) {
-    return fp32 ? launch_cls_t<float>(cls, mats, tasks, ntasks, queue, single, A, X, ipiv, jpiv,
-                                      res, zero_tol, eps_default, det_only, run_flag, s)
-                : launch_cls_t<double>(cls, mats, tasks, ntasks, queue, single, A, X, ipiv, jpiv,
-                                       res, zero_tol, eps_default, det_only, run_flag, s);
+    const bool stat = (det_only & kOnchipStaticPivots) != 0;   // FP64 only
+    det_only &= 1;
+    if (stat)
+        return fp32 ? hipErrorInvalidValue
+                    : launch_cls_t<double, true>(cls, mats, tasks, ntasks, queue, single, A, X, ipiv,
+                                                 jpiv, res, zero_tol, eps_default, det_only, run_flag, s);
+    return fp32 ? launch_cls_t<float, false>(cls, mats, tasks, ntasks, queue, single, A, X, ipiv, jpiv,
+                                             res, zero_tol, eps_default, det_only, run_flag, s)
+                : launch_cls_t<double, false>(cls, mats, tasks, ntasks, queue, single, A, X, ipiv, jpiv,
+                                              res, zero_tol, eps_default, det_only, run_flag, s);
 }
 
 // Single matrix (n <= 128) on one workgroup.
