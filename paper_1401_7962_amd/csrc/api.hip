@@ -208,14 +208,14 @@ bool big_full(const BigShape &s, bool fp32) {
     return (s.ncol + per - 1) / per == 8;
 }
 // The step kernel's chunk count for one matrix: the number of chunks its rows
-// fill, 8 or (below 1024 threads; such shapes have no counted units) 3-7, so
+// fill, 8 or (below 1024 threads; such shapes have no counted units) 2-7, so
 // that no unused chunk is loaded or looped over; else 0 (the 8-chunk kernel
 // with per-chunk tests).
 int big_full_chunks(const BigShape &s, bool fp32) {
     const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
     const int64_t ch = (s.ncol + per - 1) / per;
     if (ch == 8) return 8;
-    if (ch >= 3 && ch < 8 && s.nt < 1024 && !big_counted(s)) return (int)ch;
+    if (ch >= 2 && ch < 8 && s.nt < 1024 && !big_counted(s)) return (int)ch;
     return 0;
 }
 
@@ -225,20 +225,21 @@ int big_full_chunks(const BigShape &s, bool fp32) {
 // us per step, table rows / one register group per workgroup: 512: 20.7 / 10.4,
 // 768: 20.3 / 10.7, 1024: 21.2 / 11.0 (FP32: 22.3 / 15.1, 19.9 / 14.3,
 // 22.6 / 15.4); above 1024 the table's single-matrix rows stay (1536: 14.3
-// against 19.7).  Up to 2048, rows that fill exactly 4 register chunks (twice
-// the threads per row) take the 4-chunk kernel: FP64 us per step, 8 / 4
-// chunks: 256: 10.2 / 7.5, 512: 10.3 / 7.6, 1024: 11.0 / 9.3, 2048: 15.8 /
-// 14.2 (FP32 at 256-1024: 15.1-15.3 / 9.7-10.1); where 4 chunks would not be
-// filled (1536: 14.3 / 14.7) the 8-chunk shape stays.  allow4 = false keeps
-// the 8-chunk shape (the solve's extra right-hand-side chunk needs it).
-// GJ_BIG_ROWS and GJ_BIG_CHUNKS still override.
-BigShape single_shape(int n, bool fp32, int nt, int ncol = 0, bool allow4 = true) {
+// against 19.7).  Up to 2048 the rows are also spread over more threads (fewer
+// register chunks each, on the kernel of the chunk count they fill): FP64 us
+// per step with 8 / 4 / 2 chunks asked for: 256: 10.2 / 7.6 / 6.4, 512: 10.3 /
+// 7.7 / 6.4, 768: 9.4 / 7.9 / 8.7, 1024: 11.0 / 9.3 / 10.5, 2048: 15.8 / 14.2 /
+// 14.2; FP32 (4 / 2): 256: 10.1 / 7.7, 512: 10.1 / 7.7, 768: 8.9 / 8.5, 1024:
+// 10.5 / 8.8, 2048: 14.1 / 12.5.  allow_wide = false keeps the 8-chunk shape
+// (the solve's extra right-hand-side chunk needs it).  GJ_BIG_ROWS and
+// GJ_BIG_CHUNKS still override.
+BigShape single_shape(int n, bool fp32, int nt, int ncol = 0, bool allow_wide = true) {
     const int rows = (n <= 1024 && env_int("GJ_BIG_ROWS", 0) <= 0) ? 1 : 0;
-    BigShape s = big_shape(n, fp32, nt, ncol, rows);
-    if (allow4 && n <= 2048 && env_int("GJ_BIG_CHUNKS", 0) <= 0 && big_full_chunks(s, fp32) != 4) {
-        const BigShape s4 = big_shape(n, fp32, nt, ncol, rows, 4);
-        if (big_full_chunks(s4, fp32) == 4) s = s4;
-    }
+    int chunks = 0;
+    if (allow_wide && n <= 2048 && env_int("GJ_BIG_CHUNKS", 0) <= 0)
+        chunks = (fp32 || n <= 512) ? 2 : 4;
+    BigShape s = big_shape(n, fp32, nt, ncol, rows, chunks);
+    if (chunks && big_full_chunks(s, fp32) == 0) s = big_shape(n, fp32, nt, ncol, rows);
     return s;
 }
 

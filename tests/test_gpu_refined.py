@@ -95,12 +95,11 @@ def test_refined_counted_units(gj, stat, monkeypatch):
 
 @pytest.mark.parametrize("n", [1100, 2100, 2000, 4000])
 def test_refined_chunks_per_thread(gj, n, monkeypatch):
-    """The FP32 elimination's row shape from the tuning table (4 register
-    chunks per thread in these buckets; at 2000 and 4000 the rows fill all 4,
-    which selects the 4-chunk step kernel) against the 8-chunk shape: the
-    same FP32 pivot sequence as the oracle, and the same refined inverse bit
-    for bit (each element's update does not depend on which thread holds
-    it)."""
+    """The FP32 elimination's default row shape (2 register chunks per thread
+    up to 2048, the table's 4 above; each on the step kernel of the chunk
+    count its rows fill) against the 8-chunk shape: the same FP32 pivot
+    sequence as the oracle, and the same refined inverse bit for bit (each
+    element's update does not depend on which thread holds it)."""
     A = inputs.conditioned(n, 1e4, inputs.rng_for(0, 6070 + n))
     X4, ip4, jp4, r4 = _refined(gj, A)
     monkeypatch.setenv("GJ_BIG_CHUNKS", "8")
