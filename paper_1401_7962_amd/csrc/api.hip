@@ -474,7 +474,17 @@ BigShape blk_shape(int m, bool fp32) {
     // m / 256 everywhere (402.5 / 409.9 ms for the FP32 stage; table rows
     // above 4096: 686.9, above 7000: 687.2)
     if (fp32 && m > 6144) rows = 0;
-    return big_shape(m, fp32, big_threads(m, fp32), 0, env_int("GJ_BIG_ROWS", 0) > 0 ? 0 : rows);
+    if (env_int("GJ_BIG_ROWS", 0) > 0) rows = 0;
+    // blocks up to 2048 spread each row over more threads, as single matrices
+    // of that order do: ms per 4096^2 / 8192^2 FP64, refined 4096^2 with FP32
+    // delayed updates: 101.3 / 689.8, 128.0 without; 98.3 / 687.1, 120.9 up to
+    // 1024; 97.4 / 686.3, 121.9 up to 2048; 97.5 / 686.3, 121.1 up to 4096
+    const int wide = env_int("GJ_BLK_WIDE", 2048);   // experiments
+    if (m <= wide && env_int("GJ_BIG_CHUNKS", 0) <= 0) {
+        const BigShape s = big_shape(m, fp32, big_threads(m, fp32), 0, rows, (fp32 || m <= 512) ? 2 : 4);
+        if (big_full_chunks(s, fp32) != 0) return s;
+    }
+    return big_shape(m, fp32, big_threads(m, fp32), 0, rows);
 }
 
 struct BlkLayout {
