@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -386,7 +387,11 @@ bool plan_batch(int batch, const int32_t *n_host, bool fp32, BatchPlan &P) {
         // FP32 + refinement 926 -> 883 ms.  Splitting the groups further into
         // parts of 96-640 MB (the Infinity Cache's size) gave no consistent
         // gain (FP64 981-1109 ms, FP32 stage 895-1033 ms).
-        for (int f : {8, 7, 6, 5, 4, 3, 0}) {
+        // every key a member has, largest first (so no member is left out)
+        std::vector<int> fulls(key);
+        std::sort(fulls.begin(), fulls.end(), std::greater<int>());
+        fulls.erase(std::unique(fulls.begin(), fulls.end()), fulls.end());
+        for (int f : fulls) {
             BigGroup G;
             G.full = f;
             G.bmap0 = P.bmap.size();

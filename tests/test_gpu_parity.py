@@ -256,6 +256,18 @@ def test_batched_mixed(gj):
     assert n_sing >= len(singular) - 2   # tiny members (n < 3) cannot host the planted sum
 
 
+@pytest.mark.parametrize("chunks", ["2", "4"])
+def test_batched_chunk_groups(gj, chunks, monkeypatch):
+    """Streaming members of several orders with fewer register chunks per
+    thread than the default: the members fall into groups by the chunk count
+    their rows fill (1-4 here), one launch sequence each, and every member of
+    every group must be inverted (bit for bit against the oracle)."""
+    monkeypatch.setenv("GJ_BIG_CHUNKS", chunks)
+    rng = inputs.rng_for(0, 8600 + int(chunks))
+    mats = [rng.standard_normal((n, n)) for n in (130, 200, 257, 300, 384, 500, 64)]
+    _batched_vs_oracle(gj, mats, f"chunks={chunks}")
+
+
 def _batched_vs_oracle(gj, mats, where):
     import torch
     sizes = np.array([M.shape[0] for M in mats], dtype=np.int32)
