@@ -209,14 +209,14 @@ bool big_full(const BigShape &s, bool fp32) {
     return (s.ncol + per - 1) / per == 8;
 }
 // The step kernel's chunk count for one matrix: the number of chunks its rows
-// fill, 8 or (below 1024 threads; such shapes have no counted units) 2-7, so
+// fill, 8 or (below 1024 threads; such shapes have no counted units) 1-7, so
 // that no unused chunk is loaded or looped over; else 0 (the 8-chunk kernel
 // with per-chunk tests).
 int big_full_chunks(const BigShape &s, bool fp32) {
     const int64_t per = (int64_t)s.tpr * (fp32 ? 4 : 2);
     const int64_t ch = (s.ncol + per - 1) / per;
     if (ch == 8) return 8;
-    if (ch >= 2 && ch < 8 && s.nt < 1024 && !big_counted(s)) return (int)ch;
+    if (ch >= 1 && ch < 8 && s.nt < 1024 && !big_counted(s)) return (int)ch;
     return 0;
 }
 
@@ -230,15 +230,18 @@ int big_full_chunks(const BigShape &s, bool fp32) {
 // register chunks each, on the kernel of the chunk count they fill): FP64 us
 // per step with 8 / 4 / 2 chunks asked for: 256: 10.2 / 7.6 / 6.4, 512: 10.3 /
 // 7.7 / 6.4, 768: 9.4 / 7.9 / 8.7, 1024: 11.0 / 9.3 / 10.5, 2048: 15.8 / 14.2 /
-// 14.2; FP32 (4 / 2): 256: 10.1 / 7.7, 512: 10.1 / 7.7, 768: 8.9 / 8.5, 1024:
-// 10.5 / 8.8, 2048: 14.1 / 12.5.  allow_wide = false keeps the 8-chunk shape
-// (the solve's extra right-hand-side chunk needs it).  GJ_BIG_ROWS and
-// GJ_BIG_CHUNKS still override.
+// 14.2; FP32 (4 / 2 / 1): 256: 10.1 / 7.7 / 6.6, 512: 10.1 / 7.7 / 6.8, 768:
+// 8.9 / 8.5 / 8.9, 1024: 10.5 / 8.8 / 10.4, 2048: 14.1 / 12.5 / 12.5.
+// allow_wide = false keeps the 8-chunk shape (the solve's extra right-hand-
+// side chunk needs it).  GJ_BIG_ROWS and GJ_BIG_CHUNKS still override.
+int wide_chunks(int n, bool fp32) {
+    if (fp32) return n <= 512 ? 1 : 2;
+    return n <= 512 ? 2 : 4;
+}
 BigShape single_shape(int n, bool fp32, int nt, int ncol = 0, bool allow_wide = true) {
     const int rows = (n <= 1024 && env_int("GJ_BIG_ROWS", 0) <= 0) ? 1 : 0;
     int chunks = 0;
-    if (allow_wide && n <= 2048 && env_int("GJ_BIG_CHUNKS", 0) <= 0)
-        chunks = (fp32 || n <= 512) ? 2 : 4;
+    if (allow_wide && n <= 2048 && env_int("GJ_BIG_CHUNKS", 0) <= 0) chunks = wide_chunks(n, fp32);
     BigShape s = big_shape(n, fp32, nt, ncol, rows, chunks);
     if (chunks && big_full_chunks(s, fp32) == 0) s = big_shape(n, fp32, nt, ncol, rows);
     return s;
@@ -486,7 +489,7 @@ BigShape blk_shape(int m, bool fp32) {
     // 1024; 97.4 / 686.3, 121.9 up to 2048; 97.5 / 686.3, 121.1 up to 4096
     const int wide = env_int("GJ_BLK_WIDE", 2048);   // experiments
     if (m <= wide && env_int("GJ_BIG_CHUNKS", 0) <= 0) {
-        const BigShape s = big_shape(m, fp32, big_threads(m, fp32), 0, rows, (fp32 || m <= 512) ? 2 : 4);
+        const BigShape s = big_shape(m, fp32, big_threads(m, fp32), 0, rows, wide_chunks(m, fp32));
         if (big_full_chunks(s, fp32) != 0) return s;
     }
     return big_shape(m, fp32, big_threads(m, fp32), 0, rows);

@@ -91,7 +91,7 @@ template <typename VT, typename T>
 __device__ inline void vset(VT &x, int e, T v) { reinterpret_cast<T *>(&x)[e] = v; }
 
 // Column chunks per thread of the step kernel (its NCH): n <= NCH * V * threads-per-row.
-// 8 in general; a shape whose rows fill exactly 2-7 chunks per thread gets a kernel
+// 8 in general; a shape whose rows fill exactly 1-7 chunks per thread gets a kernel
 // of that many, whose loops and register arrays then hold no unused chunk.
 constexpr int kNch = 8;
 // Rows a thread holds in registers at once in the step kernel (their loads
@@ -835,12 +835,12 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, int full, bool counted, 
                       const BigDesc &single, const int *grid_per_step, int grid_init, int grid_finish, int max_n,
                       int gather_grid, double zero_tol, double eps_default, int det_only,
                       void *const *events, const int32_t *run_flag, hipStream_t s) {
-    // full: 0 (per-chunk tests) or the chunk count 2-8 that every row fills
+    // full: 0 (per-chunk tests) or the chunk count 1-8 that every row fills
     // exactly (below 8: 256 and 512 threads, rule 0, no counter, no B).  The
     // counter is compiled in for 8 full chunks below 1024 threads only; the
     // extra right-hand-side chunk for FP64 with 8 full chunks below 1024
     // threads, without the counter
-    if (full != 0 && (full < 2 || full > kNch)) return hipErrorInvalidValue;
+    if (full != 0 && (full < 1 || full > kNch)) return hipErrorInvalidValue;
     if (full != 0 && full != kNch && (counted || rhs || rule != 0 || nt >= 1024))
         return hipErrorInvalidValue;
     if (counted && !(full == kNch && nt < 1024)) return hipErrorInvalidValue;
@@ -872,7 +872,8 @@ hipError_t launch_big(bool fp32, int nt, bool nt_loads, int full, bool counted, 
             return nt_loads ? run_big_t<TT, NTV, true, true, true>(GJ_BIG_ARGS)                   \
                             : run_big_t<TT, NTV, false, true, true>(GJ_BIG_ARGS);                 \
         switch (full) {                                                                           \
-            GJ_BIG_NCH(TT, NTV, 2); GJ_BIG_NCH(TT, NTV, 3); GJ_BIG_NCH(TT, NTV, 4);              \
+            GJ_BIG_NCH(TT, NTV, 1); GJ_BIG_NCH(TT, NTV, 2); GJ_BIG_NCH(TT, NTV, 3);              \
+            GJ_BIG_NCH(TT, NTV, 4);                                                               \
             GJ_BIG_NCH(TT, NTV, 5);                                                               \
             GJ_BIG_NCH(TT, NTV, 6); GJ_BIG_NCH(TT, NTV, 7);                                       \
             default: break;                                                                       \

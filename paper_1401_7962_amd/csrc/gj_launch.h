@@ -33,7 +33,7 @@ hipError_t launch_onchip(bool fp32, const MatDesc *mats, const OnchipTask *tasks
                          hipStream_t s);
 
 // Streaming path: init, one step launch per k, finish, gather.  nt_loads:
-// nontemporal row loads; full: the chunk count 2-8 that every matrix's rows
+// nontemporal row loads; full: the chunk count 1-8 that every matrix's rows
 // fill exactly, else 0 (below 8: rule 0, nt < 1024, not counted, no rhs);
 // counted: some descriptor leaves work units to the
 // per-step counter (needs 8 full chunks and nt < 1024); rhs: a solve whose

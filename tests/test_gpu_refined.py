@@ -95,8 +95,8 @@ def test_refined_counted_units(gj, stat, monkeypatch):
 
 @pytest.mark.parametrize("n", [1100, 2100, 2000, 4000])
 def test_refined_chunks_per_thread(gj, n, monkeypatch):
-    """The FP32 elimination's default row shape (2 register chunks per thread
-    up to 2048, the table's 4 above; each on the step kernel of the chunk
+    """The FP32 elimination's default row shape (1-2 register chunks per
+    thread up to 2048, the table's 4 above; each on the step kernel of the chunk
     count its rows fill) against the 8-chunk shape: the same FP32 pivot
     sequence as the oracle, and the same refined inverse bit for bit (each
     element's update does not depend on which thread holds it)."""
