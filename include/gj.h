@@ -28,7 +28,10 @@
  *   path (gj_invert, gj_det with GJ_PREC_FP32_REFINED) enqueues its FP64
  *   fallback on a second stream of the device that the library creates once,
  *   and makes `stream` wait for it before the call's last work: synchronising
- *   `stream` still covers everything.  The return value covers only argument checks and
+ *   `stream` still covers everything.  gj_invert_batched (plain FP64) runs its
+ *   one-matrix-per-wavefront classes on that same stream, also under graph
+ *   capture once an earlier call outside capture has created it, and joins it
+ *   back the same way.  The return value covers only argument checks and
  *   launch errors; numeric outcomes (singular, non-finite) are reported per
  *   matrix in the device-side gj_result.
  * Pivots.  0-based, LAPACK xGETC2 convention: at step k rows k <-> ipiv[k] and

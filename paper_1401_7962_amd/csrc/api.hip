@@ -10,6 +10,7 @@
 #include <cstring>
 #include <functional>
 #include <mutex>
+#include <optional>
 #include <string>
 #include <vector>
 
@@ -795,60 +796,79 @@ RefinedLayout refined_layout(int n, bool acc = false, bool blocked = false) {
 
 #define GJ_TRY(expr) do { hipError_t e_ = (expr); if (e_ != hipSuccess) return hip_fail(e_); } while (0)
 
-// A second stream per device.  The refined path's FP64 fallback and its
-// determinant stage exclude each other (both flags are set before either
-// runs, and each touches the buffers they share only when its flag is set),
-// so outside graph capture the fallback goes to this stream and overlaps the
-// determinant stage: when it is not needed, its n step launches return at
-// once (about 1.8 us each), time the determinant stage hides.  Under capture,
-// and for gj_invert_noalloc (which creates nothing), the launches stay in
-// order on the caller's stream.
-std::mutex g_side_mu;
-hipStream_t g_side[64] = {nullptr};
+// A second stream per device, for work that can overlap the caller's stream:
+// * the refined path's FP64 fallback beside its determinant stage: the two
+//   exclude each other (both flags are set before either runs, and each
+//   touches the buffers they share only when its flag is set); when the
+//   fallback is not needed its n step launches return at once (about 1.8 us
+//   each), time the determinant stage hides (outside graph capture only);
+// * a batch's one-matrix-per-wavefront on-chip classes beside the others and
+//   the streaming members (disjoint members, their own queue counters), so
+//   that their persistent launches fill the other classes' tails (also under
+//   capture, once the stream exists).
+// gj_invert_noalloc (which creates nothing) keeps everything in order on the
+// caller's stream.
 thread_local bool g_no_side = false;
 
-hipStream_t side_stream_for(hipStream_t s) {
-    if (g_no_side) return nullptr;
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    if (s) {
-        hipDevice_t sd = 0;
-        if (hipStreamGetDevice(s, &sd) != hipSuccess || (int)sd != dev) return nullptr;
-    }
-    std::lock_guard<std::mutex> lock(g_side_mu);
-    if (!g_side[dev] && hipStreamCreateWithFlags(&g_side[dev], hipStreamNonBlocking) != hipSuccess) {
-        g_side[dev] = nullptr;
-        return nullptr;
-    }
-    return g_side[dev];
-}
-
-// The fork of the caller's stream s onto the side stream and the join back.
-struct SideFork {
-    hipStream_t s, fs;                      // fs: the stream the forked work goes to
+// One side stream per device with its fork and join events, created once
+// outside graph capture.  A fork holds the device's lock until it has joined
+// back, so that concurrent callers do not interleave on the shared events.
+struct SideRes {
+    hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
-    explicit SideFork(hipStream_t s_) : s(s_), fs(s_) {
-        hipStream_t side = side_stream_for(s);
-        if (!side) return;
-        if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess)
+    bool failed = false;
+    std::mutex mu;
+};
+SideRes g_side_res[64];
+
+// The fork of the caller's stream s onto the side stream (fs) and the join
+// back; fs == s when there is none (gj_invert_noalloc, another device's
+// stream, capture without allow_capture or before the side stream exists).
+struct SideFork {
+    hipStream_t s, fs;
+    SideRes *r = nullptr;
+    std::unique_lock<std::mutex> lock;
+    SideFork(hipStream_t s_, bool allow_capture) : s(s_), fs(s_) {
+        if (g_no_side) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess) return;
+        const bool capturing = cs != hipStreamCaptureStatusNone;
+        if (capturing && !allow_capture) return;
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+        if (s) {
+            hipDevice_t sd = 0;
+            if (hipStreamGetDevice(s, &sd) != hipSuccess || (int)sd != dev) return;
+        }
+        SideRes *x = &g_side_res[dev];
+        std::unique_lock<std::mutex> l(x->mu);
+        if (!x->s) {
+            if (capturing || x->failed) return;
+            hipStream_t st = nullptr;
+            hipEvent_t f = nullptr, j = nullptr;
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+                x->failed = true;
+                return;
+            }
+            x->s = st; x->fork = f; x->join = j;
+        }
+        if (hipEventRecord(x->fork, s) != hipSuccess || hipStreamWaitEvent(x->s, x->fork, 0) != hipSuccess)
             return;
-        if (hipEventRecord(fork, s) == hipSuccess && hipStreamWaitEvent(side, fork, 0) == hipSuccess)
-            fs = side;
+        r = x;
+        lock = std::move(l);
+        fs = x->s;
     }
     hipError_t join_back() {
         if (fs == s) return hipSuccess;
-        hipError_t e = hipEventRecord(join, fs);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+        hipError_t e = hipEventRecord(r->join, fs);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, r->join, 0);
         fs = s;
+        lock.unlock();
         return e;
     }
-    ~SideFork() {   // destruction of a pending event is deferred until it completes
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-    }
+    ~SideFork() { (void)join_back(); }   // an early error return still joins
 };
 
 // Eliminate in FP32 (the pivots and X0), refine X in FP64, FP64 determinant.
@@ -995,7 +1015,7 @@ gj_status run_refined_single(int n, const double *A, int64_t lda, double *X, int
 
     // 3. fallback: the plain FP64 elimination, only when flagged (on the side
     // stream where there is one, beside the determinant stage)
-    SideFork fork(s);
+    SideFork fork(s, false);
     if (n <= kOnchipMax) {
         MatDesc md{0, 0, 0, n, (int32_t)lda, (int32_t)(det_only ? n : ldx), 0, nullptr};
         GJ_TRY(launch_onchip(false, nullptr, nullptr, 0, nullptr, md, 1, A, det_only ? nullptr : X,
@@ -1939,17 +1959,19 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
             plan_record(ws, sig);
         }
         const double eps_default = fp32 ? 0.0 : kEps64;
+        std::optional<SideFork> fork;   // the one-matrix-per-wavefront classes beside the rest
         if (!P.tasks.empty()) {
             uint32_t *queues = reinterpret_cast<uint32_t *>(w + P.off_queue);
             hipError_t e = launch_zero_u32(queues, kOnchipClasses, s);
             if (e != hipSuccess) return hip_fail(e);
+            fork.emplace(s, true);
             const MatDesc *mats = reinterpret_cast<const MatDesc *>(w + P.off_mats);
             const OnchipTask *tasks = reinterpret_cast<const OnchipTask *>(w + P.off_tasks);
             for (int c = 0; c < kOnchipClasses; ++c) {
                 if (!P.cls_count[c]) continue;
                 e = launch_onchip_class(fp32, c, mats, tasks + P.cls_start[c], P.cls_count[c],
                                         queues + c, MatDesc(), A, X, ipiv, jpiv, res, o.zero_tol,
-                                        eps_default, 0, nullptr, s);
+                                        eps_default, 0, nullptr, onchip_class_kind(c) == 1 ? fork->fs : s);
                 if (e != hipSuccess) return hip_fail(e);
             }
         }
@@ -1957,6 +1979,10 @@ gj_status gj_invert_batched(int32_t batch, const int32_t *n_host, const int64_t 
             hipError_t e = launch_big_groups(fp32, P, reinterpret_cast<const BigDesc *>(w + P.off_descs),
                                              reinterpret_cast<const int2 *>(w + P.off_bmap), o.zero_tol,
                                              eps_default, o.events, s);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        if (fork) {
+            const hipError_t e = fork->join_back();
             if (e != hipSuccess) return hip_fail(e);
         }
         return GJ_OK;
