@@ -30,10 +30,18 @@ def _capture(fn):
     return g
 
 
+GRAPH_BATCHES = {
+    "mixed": [5, 17, 40, 64, 70, 128, 140, 260],
+    # streaming members in several chunk groups: the groups split over two streams
+    "groups": [9, 40, 130, 200, 257, 333, 420, 512],
+}
+
+
+@pytest.mark.parametrize("batch", sorted(GRAPH_BATCHES))
 @pytest.mark.parametrize("precision", [0, 1])
-def test_batched_graph_replays(gj, precision):
+def test_batched_graph_replays(gj, precision, batch):
     import torch
-    sizes = np.array([5, 17, 40, 64, 70, 128, 140, 260], dtype=np.int32)
+    sizes = np.array(GRAPH_BATCHES[batch], dtype=np.int32)
     rng = inputs.rng_for(0, 7500)
     mats = [inputs.conditioned(int(n), 1e3, rng) for n in sizes]
     offs = np.zeros(len(sizes), dtype=np.int64)
