@@ -195,9 +195,11 @@ gj_status gj_invert(int32_t n, const double *A, int64_t lda, double *X, int64_t 
  *                  n_host, opts) bytes
  * The host arrays are read during the call only.  Matrices up to the on-chip
  * limit are inverted one per workgroup (or one per wavefront) by persistent
- * launches that take them from atomic queues, largest first; larger ones go
- * through the streaming path, one launch per elimination step for all of
- * them together.  Matrices A and X are checked for overlap with each other
+ * launches, one per size class, that take them from atomic queues, largest
+ * first (the one-per-wavefront classes on the second stream described under
+ * Stream); larger ones go through the streaming path, grouped by the number
+ * of register chunks their rows fill, one launch per elimination step for
+ * each group, the groups one after another.  Matrices A and X are checked for overlap with each other
  * and with the workspace over the span the members cover.
  * Paper: as gj_invert, applied to each matrix.
  */
